@@ -1,0 +1,196 @@
+/*
+ * qst.h -- C ABI of the MI355X (gfx950) parallel pooled pCN sampler for
+ * Bayesian quantum state tomography (arXiv 2501.17334).
+ *
+ * The three main calls follow the paper's problem statement (Section
+ * "Steps"):
+ *   qst_init_problem  -- Step 1 (data: counts c_kl of K = 3^Q Pauli settings
+ *                        with D = 2^Q outcomes each) together with Steps 2-4
+ *                        (parameterisation, N(0,I) prior, multinomial
+ *                        likelihood Eq. (likelihood));
+ *   qst_run_chains    -- Step 5: R independent, non-communicating chains of
+ *                        Algorithm 2 (pCN with step-size adaptation and
+ *                        thinning), all steps in one persistent launch;
+ *   qst_pool_moments  -- Step 6 / Eq. (BME2) with phi(rho) = rho (and the
+ *                        element-wise second moments).
+ * Supporting calls: qst_loglik evaluates Eq. (likelihood) for a batch of
+ * density matrices (the probability contraction on its own), qst_acf the
+ * autocorrelation function Eq. (ACFrho) of recorded samples.
+ *
+ * Parameterisation (Gaussian/gamma-derived form of the Bures draw's
+ * replacement): x in R^d, d = 2 D^2 + D, Re Z_ij = x[jD+i],
+ * Im Z_ij = x[D^2+jD+i], v_j = x[2D^2+j]; w_j = v_j^2 / sum_k v_k^2 and
+ * rho(x) = sum_j w_j z_j z_j^dag / (z_j^dag z_j), z_j the j-th column of Z.
+ *
+ * Conventions: setting k = sum_q s_q 3^(Q-q), s in {X=0,Y=1,Z=2}; outcome
+ * l = sum_q b_q 2^(Q-q), b = 0 the +1 eigenvalue; qubit 1 is the most
+ * significant bit.  counts are indexed k*D + l.  Complex matrices are
+ * row-major with interleaved (re, im) doubles.  The "packed" real form of a
+ * Hermitian matrix holds D*D doubles, row-major: P[a][b] = Re rho_ab for
+ * a <= b and P[a][b] = Im rho_ba for a > b.
+ *
+ * Random numbers: Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
+ * counter (block, step, chain, tag << 56) with tag 0 = normals, 1 = the
+ * Metropolis-Hastings uniform, 2 = the delayed-acceptance stage-1 uniform.
+ * A uniform is ((w >> 12) + 1/2) 2^-52; normal i of a step comes from block
+ * i/4 by Box-Muller on the word pairs (0,1) and (2,3).  Step 0 draws the
+ * initial state; step j >= 1 the proposal of step j.  A chain's numbers are
+ * a function of (seed, chain index within its problem, step) only, so any
+ * subset, batch or resumed run reproduces the same chains.
+ *
+ * Errors: every call returns a qst_status; no C++ exception crosses this
+ * boundary.  On failure, outputs are unspecified and qst_last_error() gives
+ * a message (thread-local, valid until the next call on the same thread).
+ * Handles are not thread-safe.
+ */
+#ifndef QST_H
+#define QST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QST_OK = 0,
+    QST_ERR_INVALID = 1,     /* bad argument (Q out of 1..6, negative count, beta0 not in (0,1], ...) */
+    QST_ERR_NOMEM = 2,       /* device or host allocation failed */
+    QST_ERR_DEVICE = 3,      /* a HIP runtime error */
+    QST_ERR_STATE = 4,       /* call out of order (e.g. pool before any run, resume before a run) */
+    QST_ERR_UNSUPPORTED = 5  /* valid but not implemented combination */
+} qst_status;
+
+/* Arithmetic of the probability contraction p = M vec(rho).  The sum
+ * sum c log p and the acceptance test are FP64 in every mode. */
+typedef enum {
+    QST_FP64 = 0,     /* exact FP64 */
+    QST_FP32 = 1,     /* FP32 operands and accumulation, log p in FP64 */
+    QST_BF16X3 = 2    /* vec(rho) split into three BF16 parts against the exact BF16 M, FP32 accumulation */
+} qst_precision;
+
+/* How p_kl = Tr(Lambda_kl rho) is formed. */
+typedef enum {
+    QST_PATH_AUTO = 0,   /* take the tuned choice for this Q (see qst_tune_*) */
+    QST_PATH_DENSE = 1,  /* GEMM of packed vec(rho) against the KD x D^2 Pauli matrix on MFMA */
+    QST_PATH_KRON = 2    /* per-qubit (Kronecker) route: Pauli coefficients, then a 2^Q-point
+                            Walsh-Hadamard transform per setting; FP64 only */
+} qst_path;
+
+typedef struct qst_problem qst_problem;   /* opaque; owns every device buffer behind it */
+
+typedef struct {
+    int32_t n_qubits;        /* Q in 1..6 */
+    const int64_t* counts;   /* host, 3^Q * 2^Q non-negative counts, index k*D + l; copied */
+    qst_precision precision;
+    qst_path path;
+    int32_t device;          /* HIP device ordinal the handle lives on */
+} qst_problem_desc;
+
+/* Frozen MLP surrogate s(x) of log L for delayed acceptance (Christen & Fox
+ * 2005):  h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2),
+ * s = out_scale * (w3 . h2 + b3) + out_shift, gelu exact (erf form).
+ * All pointers are DEVICE pointers owned by the caller and must stay valid
+ * while a run uses them.  W1 is [h1][d] and W2 [h2][h1], row-major, BF16
+ * (uint16 bit patterns); biases and w3 are FP32. */
+typedef struct {
+    int32_t h1, h2;
+    const uint16_t* W1;
+    const float* b1;
+    const uint16_t* W2;
+    const float* b2;
+    const float* w3;
+    float b3;
+    float out_scale, out_shift;
+} qst_surrogate;
+
+typedef struct {
+    int64_t n_chains;        /* R >= 1; fixed after the first run of a handle unless resume = 0 */
+    int64_t n_steps;         /* steps run by this call (>= 0) */
+    int32_t thin;            /* T >= 1: samples enter the moments at steps j = T, 2T, ... */
+    int64_t burn_in;         /* steps j <= burn_in do not enter the moments (0 = as printed) */
+    double beta0;            /* initial pCN step size, in (0, 1] (Algorithm 2 uses 0.1) */
+    int32_t adapt_every;     /* M_A (Algorithm 2 uses 500); 0 keeps beta fixed */
+    double adapt_lo, adapt_hi, adapt_factor;   /* 0.2, 0.6, 1.1 in Algorithm 2; beta is capped at 1 */
+    int64_t adapt_until;     /* -1: adapt for the whole run; else no change after step adapt_until */
+    uint64_t seed;           /* Philox key word 0 */
+    int32_t resume;          /* 0: start new chains at step 0 (clears the moments); 1: continue */
+    const qst_surrogate* surrogate;  /* NULL: plain pCN; else delayed acceptance with this surrogate */
+    /* optional per-step trace of the first trace_chains chains (DEVICE buffers,
+     * caller-owned, [trace_chains][n_steps] each; any may be NULL):
+     * log L of the proposal (NaN when delayed acceptance did not evaluate it),
+     * log u of the Metropolis-Hastings test, accept flag. */
+    int32_t trace_chains;
+    double* trace_llprop;
+    double* trace_logu;
+    int8_t* trace_accept;
+    /* optional recording of the current state's packed rho every record_every
+     * steps for the first record_chains chains (DEVICE buffer, caller-owned,
+     * [record_chains][n_steps / record_every][D*D]) */
+    int32_t record_every;
+    int32_t record_chains;
+    double* record_buf;
+    void* stream;            /* hipStream_t the work is queued on (NULL = default stream) */
+} qst_run_desc;
+
+typedef struct {
+    int64_t proposed;          /* chain-steps run by the call */
+    int64_t accepted;
+    int64_t stage1_passed;     /* delayed acceptance: proposals that reached the exact likelihood */
+    int64_t near_threshold;    /* steps with |log u - dlogL| < 1e-8 */
+    int64_t nonfinite_chains;  /* chains whose log L is not finite after the call */
+    double beta_min, beta_max; /* over chains, after the call */
+} qst_run_stats;
+
+/* Step 1-4: validate, copy the counts to the device, build what the chosen
+ * contraction path needs (for QST_PATH_DENSE the exact KD x D^2 Pauli matrix
+ * in the chosen precision).  *out receives a new handle. */
+qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out);
+
+/* Step 5 / Algorithm 2 on every problem of the batch in ONE persistent
+ * kernel launch per call (a batch of several handles is the uneven-batch
+ * form: each problem's results are identical to running it alone).  All
+ * handles must live on the same device.  Work is queued on runs[0].stream;
+ * the call returns without waiting unless stats is non-NULL, in which case
+ * it waits and fills stats[i] for every problem. */
+qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems,
+                          const qst_run_desc* runs, qst_run_stats* stats);
+
+/* Step 6 / Eq. (BME2): pooled mean over every stored sample of every chain
+ * (host, D*D*2 interleaved complex).  Optional host outputs (NULL to skip):
+ * second = pooled E[(Re a_ij)^2], E[(Im a_ij)^2] interleaved (D*D*2);
+ * se = between-chain standard error of Re and Im of each element,
+ * sqrt(Var_r(chain mean) / R) (D*D*2); n_samples = total stored samples.
+ * Waits for the handle's last run.  QST_ERR_STATE if nothing was run. */
+qst_status qst_pool_moments(const qst_problem* p, double* mean, double* second, double* se,
+                            int64_t* n_samples);
+
+/* Copy the chains' current state to HOST buffers (NULL to skip):
+ * x [R][d], loglik [R], beta [R], n_stored [R].  Waits for the last run. */
+qst_status qst_chain_state(const qst_problem* p, double* x, double* loglik, double* beta,
+                           int64_t* n_stored);
+
+/* Eq. (likelihood) for n density matrices: rho is a DEVICE array of n
+ * complex D x D matrices (interleaved), ll_out a DEVICE array of n doubles.
+ * path/precision as in qst_problem_desc (QST_PATH_AUTO: the handle's own).
+ * Queued on `stream`. */
+qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double* ll_out,
+                      qst_path path, qst_precision precision, void* stream);
+
+/* Eq. (ACFrho) pooled over chains: records is a DEVICE array
+ * [n_chains][n_samples][D*D] of packed samples; out (HOST, l_max+1 doubles)
+ * receives c[0..l_max] with c[0] = 1 (lag sums over n = 1..N-l_max of each
+ * chain around its own mean, averaged over chains, then normalised).
+ * Waits for completion. */
+qst_status qst_acf(const double* records, int64_t n_chains, int64_t n_samples, int32_t n_qubits,
+                   int32_t l_max, double* out, void* stream);
+
+void qst_free_problem(qst_problem* p);
+const char* qst_last_error(void);
+const char* qst_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QST_H */

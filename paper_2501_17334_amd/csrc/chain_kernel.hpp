@@ -1,0 +1,519 @@
+// The fused pCN chain step on gfx950: Algorithm 2 of the paper for a tile of
+// independent chains, every step of every chain inside one kernel launch.
+//
+// Work decomposition.  A "team" of G consecutive threads owns one chain; a
+// workgroup of WG threads holds WG/G teams (G <= 64 keeps a team inside one
+// 64-wide wavefront, G = 128/256/512 spreads a large chain over several).
+// The chain state y (d = 2D^2+D doubles), the packed rho of the current
+// state and its moment sums stay in registers for the whole launch; the only
+// HBM traffic of the step loop is the count vector (read-only, L1/L2
+// resident) and the optional traces.  LDS holds, per team, the proposal y'
+// (read back as the matrix Z), the column weights, the packed rho' and the
+// Pauli coefficients.
+//
+// One step, per team (sections of the paper in brackets):
+//  1. Philox jobs: normal block b -> 4 normals of eta (Box-Muller), plus one
+//     job for the Metropolis-Hastings uniform; y' = sqrt(1-beta^2) y + beta eta
+//     [Alg. 2, proposal]
+//  2. w_j = v_j^2 / sum v^2 / |z_j|^2 and packed rho(y') = sum_j w_j z_j z_j^dag
+//     [parameterisation]
+//  3. Pauli coefficients c_mu = Tr(rho sigma_mu), 4^Q of them, each a signed
+//     sum of D entries of rho (sigma_mu has one non-zero per row)
+//  4. per setting k, p_kl = 2^-Q sum_t c_mu(k,t) (-1)^popcount(l&t): a
+//     2^Q-point Walsh-Hadamard transform across the lanes of a D-lane group
+//     (Tr(sigma_mu Lambda_kl) factorises over qubits) [Step 1, Eq. (likelihood)]
+//  5. log L(y') = sum_{c>0} c log p, team-reduced in a fixed order [Eq. (likelihood)]
+//  6. accept iff log u < log L(y') - log L(y) [Alg. 2]; adaptation every M_A
+//     steps; thinning and the moment sums [Alg. 2; Eq. (BME2)].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rng.hpp"
+
+namespace qst {
+
+__host__ __device__ constexpr int pow3(int q) { return q == 0 ? 1 : 3 * pow3(q - 1); }
+
+template <int Q>
+struct Dims {
+    static constexpr int D = 1 << Q;
+    static constexpr int D2 = D * D;
+    static constexpr int d = 2 * D2 + D;   // parameters of rho(x)
+    static constexpr int K = pow3(Q);      // Pauli settings
+    static constexpr int KD = K * D;       // projectors
+    static constexpr int NB = (d + 3) / 4; // Philox blocks of normals per step
+};
+
+// Everything a chain launch needs; plain pointers into the problem's buffers.
+struct ChainArgs {
+    const double* nd;       // [KD] counts as doubles
+    int64_t R;              // chains of the problem
+    double* x;              // [R][d] current state
+    double* ll;             // [R] log L of the current state
+    double* beta;           // [R]
+    int32_t* acc_win;       // [R] acceptances in the current adaptation window
+    double* rho_cur;        // [R][D2] packed rho of the current state
+    double* s1;             // [R][D2] sum of stored packed rho
+    double* s2;             // [R][D2] sum of squares
+    int64_t* n_stored;      // [R]
+    int64_t* n_acc;         // [R] accepts in this call
+    int64_t* n_near;        // [R] near-threshold decisions in this call
+    int64_t step_begin;     // this call runs steps step_begin+1 .. step_begin+n_steps
+    int64_t n_steps;
+    int64_t burn_in;
+    int64_t adapt_until;
+    int32_t thin;
+    int32_t adapt_every;
+    int32_t init;           // 1: draw y^0 (step 0) and evaluate it first
+    double beta0;
+    double adapt_lo, adapt_hi, adapt_factor;
+    uint64_t seed;
+    int32_t trace_chains;
+    double* tr_ll;
+    double* tr_lu;
+    int8_t* tr_acc;
+    int32_t record_every;
+    int32_t record_chains;
+    double* rec;
+};
+
+template <int Q, int G>
+struct TeamShape {
+    using Dm = Dims<Q>;
+    static_assert(G >= Dm::D, "a team must hold one D-lane transform group");
+    static_assert(G <= 64 ? (64 % G == 0) : (G % 64 == 0), "team size must tile wavefronts");
+    static constexpr int NBL = (Dm::NB + G - 1) / G;      // normal blocks per lane
+    static constexpr int NJL = (Dm::NB + 1 + G - 1) / G;  // Philox jobs per lane (normals + MH uniform)
+    static constexpr int NPL = (Dm::D2 + G - 1) / G;      // packed rho entries per lane
+    static constexpr int NFL = (Dm::KD + G - 1) / G;      // projector outputs per lane
+    static constexpr int kMisc = 24;                      // per-team scratch doubles
+    // per-team LDS: y' / Pauli coefficients, column weights, packed rho', scratch
+    static constexpr int kLds = Dm::d + Dm::D + Dm::D2 + kMisc;
+};
+
+// ---------------------------------------------------------------------------
+// team collectives (deterministic: every lane ends with the same bits)
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ double team_sum(double v, double* scratch, int lane)
+{
+    if constexpr (G <= 64) {
+#pragma unroll
+        for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        return v;
+    } else {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((lane & 63) == 0) scratch[lane >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < G / 64; ++w) s += scratch[w];
+        __syncthreads();
+        return s;
+    }
+}
+
+template <int G>
+__device__ __forceinline__ int team_or(int v, double* scratch, int lane)
+{
+    if constexpr (G <= 64) {
+#pragma unroll
+        for (int o = G / 2; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
+        return v;
+    } else {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
+        if ((lane & 63) == 0) scratch[8 + (lane >> 6)] = static_cast<double>(v);
+        __syncthreads();
+        int s = 0;
+#pragma unroll
+        for (int w = 0; w < G / 64; ++w) s |= static_cast<int>(scratch[8 + w]);
+        __syncthreads();
+        return s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stages on LDS
+// ---------------------------------------------------------------------------
+
+// Column weights and packed rho from the parameters in ybuf (x layout).
+// rp[e] receives packed entry lane + G e; the packed matrix also goes to rhoP.
+template <int Q, int G>
+__device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double* rhoP,
+                                          double (&rp)[TeamShape<Q, G>::NPL], int lane)
+{
+    using Dm = Dims<Q>;
+    using S = TeamShape<Q, G>;
+    constexpr int D = Dm::D, D2 = Dm::D2;
+    double V = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < D; ++j) {
+        const double v = ybuf[2 * D2 + j];
+        V += v * v;
+    }
+    for (int j = lane; j < D; j += G) {
+        double nz = 0.0;
+        for (int i = 0; i < D; ++i) {
+            const double re = ybuf[j * D + i];
+            const double im = ybuf[D2 + j * D + i];
+            nz += re * re + im * im;
+        }
+        const double v = ybuf[2 * D2 + j];
+        wt[j] = (v * v / V) / nz;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < S::NPL; ++e) {
+        const int p = lane + G * e;
+        double acc = 0.0;
+        if (p < D2) {
+            const int a = p / D, b = p % D;
+            const int r = a <= b ? a : b;   // row of the upper-triangle element
+            const int c = a <= b ? b : a;
+            const bool want_re = a <= b;
+            for (int j = 0; j < D; ++j) {
+                const double zr_r = ybuf[j * D + r], zi_r = ybuf[D2 + j * D + r];
+                const double zr_c = ybuf[j * D + c], zi_c = ybuf[D2 + j * D + c];
+                // z_r conj(z_c): real part and imaginary part
+                const double re = zr_r * zr_c + zi_r * zi_c;
+                const double im = zi_r * zr_c - zr_r * zi_c;
+                acc += wt[j] * (want_re ? re : im);
+            }
+            rhoP[p] = acc;
+        }
+        rp[e] = acc;
+    }
+}
+
+// Pauli coefficients c_mu = Tr(rho sigma_mu), mu = sum_q mu_q 4^(Q-1-q) with
+// mu_q in {I=0, X=1, Y=2, Z=3}.  (sigma_mu)_{a^m, a} = i^nY (-1)^popcount(a & zy)
+// where m marks X/Y qubits and zy marks Z/Y qubits, so
+// c_mu = Re[i^nY sum_a (-1)^popcount(a&zy) rho_{a, a^m}].
+template <int Q, int G>
+__device__ __forceinline__ void stage_pauli(const double* rhoP, double* pauli, int lane)
+{
+    using Dm = Dims<Q>;
+    constexpr int D = Dm::D, D2 = Dm::D2;
+    for (int mu = lane; mu < D2; mu += G) {
+        int m = 0, zy = 0, nY = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int dig = (mu >> (2 * (Q - 1 - q))) & 3;
+            const int bit = 1 << (Q - 1 - q);
+            if (dig == 1 || dig == 2) m |= bit;
+            if (dig == 2 || dig == 3) zy |= bit;
+            nY += (dig == 2);
+        }
+        const bool odd = nY & 1;
+        double s = 0.0;
+        for (int a = 0; a < D; ++a) {
+            const int b = a ^ m;
+            const int lo = a < b ? a : b, hi = a < b ? b : a;
+            // even nY: Re rho_ab = P[lo][hi]; odd nY: Im rho_ab = +-P[hi][lo] (a != b)
+            const int idx = odd ? hi * D + lo : lo * D + hi;
+            const double sgn_im = (odd && a > b) ? -1.0 : 1.0;
+            const double sgn_z = (__popc(a & zy) & 1) ? -1.0 : 1.0;
+            s += (sgn_z * sgn_im) * rhoP[idx];
+        }
+        // i^nY: nY%4 = 0 -> +Re S, 1 -> -Im S, 2 -> -Re S, 3 -> +Im S
+        const int r4 = nY & 3;
+        pauli[mu] = (r4 == 1 || r4 == 2) ? -s : s;
+    }
+}
+
+// Probabilities of every projector by a 2^Q-point Walsh-Hadamard transform
+// per setting across lanes, and the partial sum of c log p of this lane.
+template <int Q, int G>
+__device__ __forceinline__ void stage_loglik(const double* pauli, const double* __restrict__ nd,
+                                             int lane, double& part, int& bad)
+{
+    using Dm = Dims<Q>;
+    using S = TeamShape<Q, G>;
+    constexpr int D = Dm::D, KD = Dm::KD;
+    const int i = lane & (D - 1);  // position inside the D-lane group (= outcome l)
+#pragma unroll 2
+    for (int e = 0; e < S::NFL; ++e) {
+        const int f = lane + G * e;
+        const bool valid = f < KD;
+        const int k = valid ? f / D : 0;
+        int mu = 0, kk = k;
+#pragma unroll
+        for (int q = Q - 1; q >= 0; --q) {
+            const int s = kk % 3;
+            kk /= 3;
+            if ((i >> (Q - 1 - q)) & 1) mu += (s + 1) << (2 * (Q - 1 - q));
+        }
+        double val = valid ? pauli[mu] : 0.0;
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const double other = __shfl_xor(val, 1 << s, 64);
+            val = ((i >> s) & 1) ? other - val : val + other;
+        }
+        const double p = val * (1.0 / D);
+        if (valid) {
+            const double n = nd[f];
+            if (n > 0.0) {
+                if (p > 0.0) part += n * log(p);
+                else bad = 1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the chain tile
+// ---------------------------------------------------------------------------
+template <int Q, int G, int WG>
+__device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
+{
+    using Dm = Dims<Q>;
+    using S = TeamShape<Q, G>;
+    constexpr int D2 = Dm::D2, d = Dm::d, NB = Dm::NB;
+    static_assert(WG % G == 0, "workgroup must hold whole teams");
+
+    const int tid = threadIdx.x;
+    const int team = tid / G;
+    const int lane = tid % G;
+    const int64_t chain = tile_chain0 + team;
+    const bool live = chain < A.R;
+    const int64_t c = live ? chain : 0;
+
+    double* ybuf = lds + team * S::kLds;
+    double* wt = ybuf + d;
+    double* rhoP = wt + Dm::D;
+    double* misc = rhoP + D2;
+    double* pauli = ybuf;  // reuses the parameter buffer once rho is built
+
+    double y[S::NBL * 4];
+    double yp[S::NBL * 4];
+    double rc[S::NPL], rp[S::NPL], s1[S::NPL], s2[S::NPL];
+    double ll, beta;
+    int acc_w;
+    int64_t nst, nacc = 0, nnear = 0;
+
+    // evaluate log L at the parameters in yp (team-uniform result)
+    auto evaluate = [&]() -> double {
+#pragma unroll
+        for (int e = 0; e < S::NBL; ++e) {
+            const int b = lane + G * e;
+            if (b < NB) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int i = 4 * b + w;
+                    if (i < d) ybuf[i] = yp[4 * e + w];
+                }
+            }
+        }
+        __syncthreads();
+        stage_rho<Q, G>(ybuf, wt, rhoP, rp, lane);
+        __syncthreads();
+        stage_pauli<Q, G>(rhoP, pauli, lane);
+        __syncthreads();
+        double part = 0.0;
+        int bad = 0;
+        stage_loglik<Q, G>(pauli, A.nd, lane, part, bad);
+        const double tot = team_sum<G>(part, misc + 4, lane);
+        const int anybad = team_or<G>(bad, misc + 4, lane);
+        return anybad ? -INFINITY : tot;
+    };
+
+    // Philox jobs of a step: normal blocks 0..NB-1, then the MH uniform (job NB)
+    auto draw = [&](uint64_t step, double a, double bt, bool initial) {
+#pragma unroll
+        for (int e = 0; e < S::NJL; ++e) {
+            const int job = lane + G * e;
+            const bool normal = job < NB;
+            const uint64_t c0 = normal ? static_cast<uint64_t>(job) : 0;
+            const uint64_t c3 = normal ? 0 : (static_cast<uint64_t>(kTagMH) << 56);
+            if (job <= NB) {
+                const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(c), c3, A.seed, 0);
+                if (normal) {
+                    double n[4];
+                    box_muller(B.w[0], B.w[1], n[0], n[1]);
+                    box_muller(B.w[2], B.w[3], n[2], n[3]);
+                    if (e < S::NBL) {
+#pragma unroll
+                        for (int w = 0; w < 4; ++w)
+                            yp[4 * e + w] = initial ? n[w] : a * y[4 * e + w] + bt * n[w];
+                    }
+                } else {
+                    misc[0] = uniform_open(B.w[0]);
+                }
+            }
+        }
+    };
+
+    // ---- load or initialise the chain state ----
+    if (A.init) {
+#pragma unroll
+        for (int e = 0; e < S::NBL * 4; ++e) y[e] = 0.0;
+        draw(0, 0.0, 1.0, true);
+        ll = evaluate();
+#pragma unroll
+        for (int e = 0; e < S::NBL * 4; ++e) y[e] = yp[e];
+#pragma unroll
+        for (int e = 0; e < S::NPL; ++e) {
+            rc[e] = rp[e];
+            s1[e] = 0.0;
+            s2[e] = 0.0;
+        }
+        beta = A.beta0;
+        acc_w = 0;
+        nst = 0;
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int e = 0; e < S::NBL; ++e) {
+            const int b = lane + G * e;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int i = 4 * b + w;
+                y[4 * e + w] = (b < NB && i < d) ? A.x[c * d + i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < S::NPL; ++e) {
+            const int p = lane + G * e;
+            const bool ok = p < D2;
+            rc[e] = ok ? A.rho_cur[c * D2 + p] : 0.0;
+            s1[e] = ok ? A.s1[c * D2 + p] : 0.0;
+            s2[e] = ok ? A.s2[c * D2 + p] : 0.0;
+        }
+        ll = A.ll[c];
+        beta = A.beta[c];
+        acc_w = A.acc_win[c];
+        nst = A.n_stored[c];
+    }
+
+    const int64_t n_rec = A.record_every > 0 ? A.n_steps / A.record_every : 0;
+
+    // ---- Algorithm 2 ----
+    for (int64_t t = 0; t < A.n_steps; ++t) {
+        const int64_t j = A.step_begin + 1 + t;
+        const double a = sqrt(1.0 - beta * beta);
+        draw(static_cast<uint64_t>(j), a, beta, false);
+        const double llp = evaluate();
+        const double logu = log(misc[0]);
+        const double delta = llp - ll;
+        const bool accept = logu < delta;
+        nnear += fabs(logu - delta) < 1e-8 ? 1 : 0;
+        if (accept) {
+#pragma unroll
+            for (int e = 0; e < S::NBL * 4; ++e) y[e] = yp[e];
+#pragma unroll
+            for (int e = 0; e < S::NPL; ++e) rc[e] = rp[e];
+            ll = llp;
+            ++acc_w;
+            ++nacc;
+        }
+        if (A.adapt_every > 0 && j % A.adapt_every == 0) {
+            if (A.adapt_until < 0 || j <= A.adapt_until) {
+                const double rate = static_cast<double>(acc_w) / static_cast<double>(A.adapt_every);
+                if (rate > A.adapt_hi) beta = fmin(beta * A.adapt_factor, 1.0);
+                if (rate < A.adapt_lo) beta = beta / A.adapt_factor;
+            }
+            acc_w = 0;
+        }
+        if (j > A.burn_in && j % A.thin == 0) {
+#pragma unroll
+            for (int e = 0; e < S::NPL; ++e) {
+                s1[e] += rc[e];
+                s2[e] += rc[e] * rc[e];
+            }
+            ++nst;
+        }
+        if (live && chain < A.trace_chains && lane == 0) {
+            const int64_t o = chain * A.n_steps + t;
+            if (A.tr_ll) A.tr_ll[o] = llp;
+            if (A.tr_lu) A.tr_lu[o] = logu;
+            if (A.tr_acc) A.tr_acc[o] = accept ? 1 : 0;
+        }
+        if (A.record_every > 0 && live && chain < A.record_chains && (t + 1) % A.record_every == 0) {
+            const int64_t slot = (t + 1) / A.record_every - 1;
+            double* dst = A.rec + (chain * n_rec + slot) * D2;
+#pragma unroll
+            for (int e = 0; e < S::NPL; ++e) {
+                const int p = lane + G * e;
+                if (p < D2) dst[p] = rc[e];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- write the state back ----
+    if (live) {
+#pragma unroll
+        for (int e = 0; e < S::NBL; ++e) {
+            const int b = lane + G * e;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int i = 4 * b + w;
+                if (b < NB && i < d) A.x[c * d + i] = y[4 * e + w];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < S::NPL; ++e) {
+            const int p = lane + G * e;
+            if (p < D2) {
+                A.rho_cur[c * D2 + p] = rc[e];
+                A.s1[c * D2 + p] = s1[e];
+                A.s2[c * D2 + p] = s2[e];
+            }
+        }
+        if (lane == 0) {
+            A.ll[c] = ll;
+            A.beta[c] = beta;
+            A.acc_win[c] = acc_w;
+            A.n_stored[c] = nst;
+            A.n_acc[c] = nacc;
+            A.n_near[c] = nnear;
+        }
+    }
+}
+
+template <int Q, int G, int WG>
+__global__ __launch_bounds__(WG) void k_chains(ChainArgs A)
+{
+    extern __shared__ double lds[];
+    chain_tile<Q, G, WG>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds);
+}
+
+// Eq. (likelihood) for n given density matrices (complex, interleaved,
+// row-major), one team per matrix.
+template <int Q, int G, int WG>
+__global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, const double* rho,
+                                               int64_t n, double* ll_out)
+{
+    using Dm = Dims<Q>;
+    using S = TeamShape<Q, G>;
+    constexpr int D = Dm::D, D2 = Dm::D2;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x, team = tid / G, lane = tid % G;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * (WG / G) + team;
+    const bool live = idx < n;
+    const int64_t c = live ? idx : 0;
+    double* pauli = lds + team * S::kLds;
+    double* rhoP = pauli + Dm::d + D;
+    double* misc = rhoP + D2;
+    for (int p = lane; p < D2; p += G) {
+        const int a = p / D, b = p % D;
+        // packed: Re rho_ab above/on the diagonal, Im rho_ba below it
+        rhoP[p] = a <= b ? rho[(c * D2 + a * D + b) * 2] : rho[(c * D2 + b * D + a) * 2 + 1];
+    }
+    __syncthreads();
+    stage_pauli<Q, G>(rhoP, pauli, lane);
+    __syncthreads();
+    double part = 0.0;
+    int bad = 0;
+    stage_loglik<Q, G>(pauli, nd, lane, part, bad);
+    const double tot = team_sum<G>(part, misc + 4, lane);
+    const int anybad = team_or<G>(bad, misc + 4, lane);
+    if (live && lane == 0) ll_out[idx] = anybad ? -INFINITY : tot;
+}
+
+}  // namespace qst

@@ -1,0 +1,86 @@
+// Counter-based random numbers for the chain kernels (gfx950).
+//
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11): ten rounds of the two-multiply bijection, the key
+// bumped by the two Weyl constants between rounds.  Every random number a
+// chain uses is a pure function of (seed, chain, step, block, tag), so a chain
+// needs no stored generator state and any subset of chains, any batch layout
+// and any split of a run into several calls reproduce the same numbers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qst {
+
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ULL;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ULL;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ULL;
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73BULL;
+
+// Stream tags (counter word 3, bits 56..63).
+constexpr int kTagNormal = 0;
+constexpr int kTagMH = 1;
+constexpr int kTagDA = 2;
+
+struct Block4 {
+    uint64_t w[4];
+};
+
+__device__ __forceinline__ Block4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                                 uint64_t k0, uint64_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint64_t lo0 = kPhiloxM0 * c0;
+        const uint64_t hi0 = __umul64hi(kPhiloxM0, c0);
+        const uint64_t lo1 = kPhiloxM1 * c2;
+        const uint64_t hi1 = __umul64hi(kPhiloxM1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0;
+        const uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    Block4 b;
+    b.w[0] = c0;
+    b.w[1] = c1;
+    b.w[2] = c2;
+    b.w[3] = c3;
+    return b;
+}
+
+// Block `block` of stream `tag` for (chain, step): counter (block, step,
+// chain, tag << 56), key (seed, 0).
+__device__ __forceinline__ Block4 stream_block(uint64_t seed, int tag, uint64_t block, uint64_t step,
+                                               uint64_t chain)
+{
+    return philox4x64_10(block, step, chain, static_cast<uint64_t>(tag) << 56, seed, 0);
+}
+
+// Uniform on the open interval (0,1): top 52 bits plus one half, times 2^-52
+// (exact in FP64, so the result is never 0 or 1).
+__device__ __forceinline__ double uniform_open(uint64_t w)
+{
+    return (static_cast<double>(w >> 12) + 0.5) * 0x1.0p-52;
+}
+
+// Box-Muller (1958) on one pair of words: r = sqrt(-2 ln u_a),
+// theta = 2 pi u_b -> (r cos theta, r sin theta).
+__device__ __forceinline__ void box_muller(uint64_t wa, uint64_t wb, double& n0, double& n1)
+{
+    const double ua = uniform_open(wa);
+    const double ub = uniform_open(wb);
+    const double r = sqrt(-2.0 * log(ua));
+    double s, c;
+    sincos(2.0 * M_PI * ub, &s, &c);
+    n0 = r * c;
+    n1 = r * s;
+}
+
+}  // namespace qst

@@ -1,0 +1,215 @@
+"""Thin Python binding of the C ABI in include/qst.h (argument marshalling only).
+
+Every computation runs in libqst.so's HIP kernels; this module converts
+Python arguments to the C structs, passes torch device pointers and the
+current HIP stream, and raises on any non-zero status.  If libqst.so is
+missing it raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqst.so")
+
+QST_OK, QST_ERR_INVALID, QST_ERR_NOMEM, QST_ERR_DEVICE, QST_ERR_STATE, QST_ERR_UNSUPPORTED = range(6)
+FP64, FP32, BF16X3 = 0, 1, 2
+PATH_AUTO, PATH_DENSE, PATH_KRON = 0, 1, 2
+
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+_PATH = {"auto": PATH_AUTO, "dense": PATH_DENSE, "kron": PATH_KRON}
+
+
+class QstError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qst status {status}: {msg}")
+        self.status = status
+
+
+class _ProblemDesc(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("counts", C.POINTER(C.c_int64)),
+                ("precision", C.c_int), ("path", C.c_int), ("device", C.c_int32)]
+
+
+class _Surrogate(C.Structure):
+    _fields_ = [("h1", C.c_int32), ("h2", C.c_int32), ("W1", C.c_void_p), ("b1", C.c_void_p),
+                ("W2", C.c_void_p), ("b2", C.c_void_p), ("w3", C.c_void_p), ("b3", C.c_float),
+                ("out_scale", C.c_float), ("out_shift", C.c_float)]
+
+
+class _RunDesc(C.Structure):
+    _fields_ = [("n_chains", C.c_int64), ("n_steps", C.c_int64), ("thin", C.c_int32),
+                ("burn_in", C.c_int64), ("beta0", C.c_double), ("adapt_every", C.c_int32),
+                ("adapt_lo", C.c_double), ("adapt_hi", C.c_double), ("adapt_factor", C.c_double),
+                ("adapt_until", C.c_int64), ("seed", C.c_uint64), ("resume", C.c_int32),
+                ("surrogate", C.POINTER(_Surrogate)), ("trace_chains", C.c_int32),
+                ("trace_llprop", C.c_void_p), ("trace_logu", C.c_void_p), ("trace_accept", C.c_void_p),
+                ("record_every", C.c_int32), ("record_chains", C.c_int32), ("record_buf", C.c_void_p),
+                ("stream", C.c_void_p)]
+
+
+class _RunStats(C.Structure):
+    _fields_ = [("proposed", C.c_int64), ("accepted", C.c_int64), ("stage1_passed", C.c_int64),
+                ("near_threshold", C.c_int64), ("nonfinite_chains", C.c_int64),
+                ("beta_min", C.c_double), ("beta_max", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqst.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_2501_17334_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.qst_init_problem.argtypes = [C.POINTER(_ProblemDesc), C.POINTER(vp)]
+        L.qst_run_chains.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_RunDesc), C.POINTER(_RunStats)]
+        L.qst_pool_moments.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.qst_chain_state.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.qst_loglik.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_int, vp]
+        L.qst_acf.argtypes = [vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
+        L.qst_free_problem.argtypes = [vp]
+        L.qst_free_problem.restype = None
+        L.qst_last_error.restype = C.c_char_p
+        L.qst_version.restype = C.c_char_p
+        for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state",
+                  "qst_loglik", "qst_acf"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != QST_OK:
+        raise QstError(status, lib().qst_last_error().decode())
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _f64(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class RunConfig:
+    n_chains: int
+    n_steps: int
+    seed: int
+    beta0: float = 0.1
+    thin: int = 1
+    burn_in: int = 0
+    adapt_every: int = 500
+    adapt_lo: float = 0.2
+    adapt_hi: float = 0.6
+    adapt_factor: float = 1.1
+    adapt_until: int = -1
+    resume: bool = False
+
+
+class Problem:
+    """A tomography problem on one GPU (qst_init_problem / qst_free_problem)."""
+
+    def __init__(self, n_qubits, counts, precision="fp64", path="auto", device=0):
+        self.Q = int(n_qubits)
+        self.D = 2 ** self.Q
+        self.K = 3 ** self.Q
+        self.d = 2 * self.D * self.D + self.D
+        self.counts = np.ascontiguousarray(counts, dtype=np.int64).reshape(-1)
+        if self.counts.size != self.K * self.D:
+            raise ValueError("counts must have 3^Q * 2^Q entries")
+        desc = _ProblemDesc(self.Q, self.counts.ctypes.data_as(C.POINTER(C.c_int64)),
+                            _PREC[precision], _PATH[path], device)
+        h = C.c_void_p()
+        _check(lib().qst_init_problem(C.byref(desc), C.byref(h)))
+        self._h = h
+        self.n_chains = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qst_free_problem(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _run_desc(self, cfg: RunConfig, trace=None, record=None, stream=None):
+        trace = trace or {}
+        record = record or {}
+        return _RunDesc(cfg.n_chains, cfg.n_steps, cfg.thin, cfg.burn_in, cfg.beta0, cfg.adapt_every,
+                        cfg.adapt_lo, cfg.adapt_hi, cfg.adapt_factor, cfg.adapt_until, cfg.seed,
+                        1 if cfg.resume else 0, None, trace.get("chains", 0),
+                        _dptr(trace.get("llprop")), _dptr(trace.get("logu")),
+                        _dptr(trace.get("accept")), record.get("every", 0), record.get("chains", 0),
+                        _dptr(record.get("buf")), stream if stream is not None else current_stream())
+
+    def run(self, cfg: RunConfig, trace=None, record=None, stats=True, stream=None):
+        """qst_run_chains on this problem alone.  trace: dict(chains=k, llprop=,
+        logu=, accept=) torch device tensors [k, n_steps]; record: dict(every=,
+        chains=, buf=) torch device tensor [chains, n_steps // every, D, D]."""
+        rd = _run_desc(self, cfg, trace, record, stream)
+        arr = (C.c_void_p * 1)(self._h)
+        st = _RunStats()
+        _check(lib().qst_run_chains(arr, 1, C.byref(rd), C.byref(st) if stats else None))
+        self.n_chains = cfg.n_chains
+        if stats:
+            return {f: getattr(st, f) for f, _ in _RunStats._fields_}
+        return None
+
+    def pool(self):
+        """qst_pool_moments: mean rho, second moments, standard errors."""
+        D2 = self.D * self.D
+        mean = np.zeros(2 * D2)
+        second = np.zeros(2 * D2)
+        se = np.zeros(2 * D2)
+        n = C.c_int64()
+        _check(lib().qst_pool_moments(self._h, _f64(mean), _f64(second), _f64(se), C.byref(n)))
+        cplx = np.array([1.0, 1j])
+        return {"mean": mean.reshape(self.D, self.D, 2) @ cplx,
+                "second_re": second.reshape(self.D, self.D, 2)[..., 0],
+                "second_im": second.reshape(self.D, self.D, 2)[..., 1],
+                "se_re": se.reshape(self.D, self.D, 2)[..., 0],
+                "se_im": se.reshape(self.D, self.D, 2)[..., 1],
+                "n_samples": int(n.value)}
+
+    def state(self):
+        """qst_chain_state: (x [R, d], loglik [R], beta [R], n_stored [R])."""
+        R = self.n_chains
+        x = np.zeros((R, self.d))
+        ll = np.zeros(R)
+        beta = np.zeros(R)
+        nst = np.zeros(R, dtype=np.int64)
+        _check(lib().qst_chain_state(self._h, _f64(x), _f64(ll), _f64(beta),
+                                     nst.ctypes.data_as(C.POINTER(C.c_int64))))
+        return x, ll, beta, nst
+
+    def loglik(self, rho_dev, out_dev, path="auto", precision="fp64", stream=None):
+        """qst_loglik on torch device tensors: rho [n, D, D] complex128 (or
+        float64 [n, D, D, 2]), out float64 [n]."""
+        n = out_dev.numel()
+        _check(lib().qst_loglik(self._h, C.c_void_p(rho_dev.data_ptr()), n, C.c_void_p(out_dev.data_ptr()),
+                                _PATH[path], _PREC[precision],
+                                stream if stream is not None else current_stream()))
+
+
+def _run_desc(problem, cfg, trace, record, stream):
+    return problem._run_desc(cfg, trace, record, stream)

@@ -57,6 +57,18 @@ def haar_vector(D, rng):
     return g / np.linalg.norm(g)
 
 
+def random_density_matrix(D, rng, rank=None):
+    """A random density matrix: Haar vectors mixed with random weights."""
+    rank = D if rank is None else rank
+    w = rng.uniform(0.05, 1.0, rank)
+    w /= w.sum()
+    rho = np.zeros((D, D), dtype=complex)
+    for i in range(rank):
+        v = haar_vector(D, rng)
+        rho += w[i] * np.outer(v, v.conj())
+    return rho
+
+
 def ghz_vector(Q):
     v = np.zeros(2 ** Q, dtype=complex)
     v[0] = v[-1] = 1.0 / np.sqrt(2.0)
