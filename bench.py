@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the pooled pCN tomography sampler on one MI355X.
+
+One bench step = the whole hot path on the 4-qubit workload: initialise
+65536 chains (step 0), run 10^4 pCN steps of Algorithm 2 on each (proposal,
+rho, Pauli probabilities, FP64 log-likelihood, accept, adaptation, moments,
+recording of 256 chains every 8 steps) in one persistent launch, then pool
+(Eq. (BME2)).  Inputs are synthetic (seeded multinomial counts of
+0.95|GHZ_4><GHZ_4| + 0.05 I/16, 1024 shots x 81 settings) and resident in HBM.
+
+Prints one JSON line: chain-steps/s as `value`, pooled ESS/s beside it, the
+roofline of the chain kernel and the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (published)
+
+
+def flops_per_chain_step(Q, stored_fraction):
+    """Algorithmic FP64 flops of one chain-step (roofline)."""
+    D = 2 ** Q
+    d = 2 * D * D + D
+    KD = 6 ** Q
+    proposal = 2 * d                       # a*y + beta*eta
+    weights = 4 * D * D + 3 * D            # column norms, v^2 / sum / |z|^2
+    rho = 4 * D ** 3                       # Hermitian rank-D update (complex)
+    contraction = sum(8 * 6 ** q * 4 ** (Q - q) for q in range(1, Q + 1))  # per-qubit 4->6 maps
+    loglik = 2 * KD                        # c * log p, summed
+    moments = 3 * D * D * stored_fraction  # S1 += rho, S2 += rho^2
+    return proposal + weights + rho + contraction + loglik + moments
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2501_17334_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_hash, key):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(key)
+    if not ent or ent.get("kernel_source_hash") != kernel_hash:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def pilot_beta(qst, P, seed, n_chains=256, n_steps=6000):
+    """Algorithm 2's own adaptation (every 100 steps here) run on a pilot set
+    of chains; the median final beta starts the measured run."""
+    import numpy as np
+    st = P.run(qst.RunConfig(n_chains=n_chains, n_steps=n_steps, seed=seed + 7919, beta0=0.1,
+                             adapt_every=100), stats=True)
+    _, _, beta, _ = P.state()
+    return float(np.median(beta)), st
+
+
+def cpu_baseline(prob, target_s):
+    """The FP64 oracle on this host's cores, on a bounded sample of the same
+    workload: 16 x threads chains from step 0, steps sized for ~target_s."""
+    from oracle import oracle as O
+    threads = O.num_threads()
+    R = 16 * threads
+    ch = O.Chains(prob.n_qubits, prob.counts, O.RunParams(n_chains=R, n_steps=0, seed=prob.seed,
+                                                          beta0=0.01, adapt_every=500))
+    t0 = time.perf_counter()
+    ch.run(2)
+    rate = 2 * R / (time.perf_counter() - t0)
+    steps = max(4, int(target_s * rate / R))
+    t0 = time.perf_counter()
+    ch.run(steps)
+    dt = time.perf_counter() - t0
+    return {"value": R * steps / dt, "unit": "chain-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{R} chains x {steps} pCN steps of the 4-qubit workload (steps 3..{steps + 2}), "
+                      f"{dt:.1f} s of FP64 CPU work"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--chains", type=int, default=None)
+    ap.add_argument("--nsteps", type=int, default=10000)
+    ap.add_argument("--burn-in", type=int, default=2000)
+    ap.add_argument("--path", default="auto")
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the chains need no "
+              f"communication, see DESIGN.md for how the run would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2501_17334_amd import qst, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = synth.make_problem(args.config, n_chains=args.chains)
+    Q, D = prob.n_qubits, 2 ** prob.n_qubits
+    R, NT, burn = prob.n_chains, args.nsteps, args.burn_in
+    P = qst.Problem(Q, prob.counts, precision=args.precision, path=args.path)
+
+    print(f"[bench] workload {args.config}: Q={Q} chains={R} steps={NT}; pilot", file=sys.stderr, flush=True)
+    beta, pst = pilot_beta(qst, P, prob.seed)
+    print(f"[bench] pilot beta={beta:.5g} (acceptance {pst['accepted'] / pst['proposed']:.3f})",
+          file=sys.stderr, flush=True)
+
+    rec_every, rec_chains = 8, min(256, R)
+    rec = torch.zeros((rec_chains, NT // rec_every, D, D), dtype=torch.float64, device=dev)
+    cfg = qst.RunConfig(n_chains=R, n_steps=NT, seed=prob.seed, beta0=beta, thin=1, burn_in=burn,
+                        adapt_every=500)
+    record = dict(every=rec_every, chains=rec_chains, buf=rec)
+
+    def step():
+        P.run(cfg, record=record, stats=False)
+
+    for w in range(args.warmup):
+        step()
+        P.pool()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    k_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    pool = None
+    for k in range(args.steps):
+        k_ev[k][0].record(stream)
+        step()
+        k_ev[k][1].record(stream)
+        pool = P.pool()          # waits for the run
+        print(f"[bench] step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    ms_kernel = float(np.mean([a.elapsed_time(b) for a, b in k_ev]))
+    chain_steps = R * NT
+    value = chain_steps / (ms_step / 1e3)
+
+    # pooled ESS: Eq. (IACT) on the recorded chains after burn-in (spacing 8 steps)
+    first = (burn + rec_every - 1) // rec_every
+    n_rec = NT // rec_every - first
+    l_max = min(200, n_rec - 1)
+    c = qst.acf(rec[:, first:].contiguous(), l_max=l_max)
+    tau = qst.iact(c)
+    n_eff = n_rec * R / tau
+    var = np.concatenate([(pool["second_re"] - pool["mean"].real ** 2).ravel(),
+                          (pool["second_im"] - pool["mean"].imag ** 2).ravel()])
+    se2 = np.concatenate([pool["se_re"].ravel() ** 2, pool["se_im"].ravel() ** 2])
+    ess_between = float(np.sum(var) / np.sum(se2))
+
+    stored_fraction = (NT - burn) / NT
+    flop = flops_per_chain_step(Q, stored_fraction)
+    achieved = flop * chain_steps / (ms_kernel / 1e3) / 1e12
+    khash = kernel_source_hash()
+    traffic = measured_traffic(khash, f"chain_kernel_q{Q}_{args.config}")
+
+    out = {
+        "metric": "pooled ESS/s and pCN chain-steps/s, 4-qubit QST, plain FP64 vs chosen form",
+        "value": value,
+        "unit": "chain-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config}: {Q}-qubit Pauli tomography ({3 ** Q} settings x {D} outcomes, "
+                        f"{prob.shots} shots/setting, seeded counts); {R} chains x {NT} pCN steps, "
+                        f"burn-in {burn}, moments every step, {rec_chains} chains recorded every "
+                        f"{rec_every} steps",
+            "n_chains": R, "n_steps": NT, "path": args.path, "precision": args.precision,
+            "beta0_from_pilot": beta,
+        },
+        "ess_per_s": n_eff / (ms_step / 1e3),
+        "ess": {"n_eff": n_eff, "tau": tau, "tau_spacing_steps": rec_every, "l_max": l_max,
+                "c_lmax": float(c[-1]), "upper_bound": bool(c[-1] > 0.05),
+                "between_chain_ess": ess_between,
+                "between_chain_ess_per_s": ess_between / (ms_step / 1e3)},
+        "acceptance_note": "adaptation per Algorithm 2 (M_A=500) from the pilot beta",
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": f"k_chains<Q={Q}>", "kernel_ms": ms_kernel,
+                     "flop_per_chain_step": flop, "kernel_source_hash": khash},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

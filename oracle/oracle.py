@@ -78,6 +78,7 @@ def lib():
         L.orc_run_chains.argtypes = [C.POINTER(_RunDesc), C.POINTER(_State)]
         L.orc_eval_batch.argtypes = [C.c_int, c_int64_p, C.c_int64, c_double_p, c_double_p,
                                      c_double_p]
+        L.orc_num_threads.restype = C.c_int
         L.orc_pool.argtypes = [C.c_int, C.c_int64, c_double_p, c_double_p, c_int64_p,
                                c_double_p, c_double_p]
         _lib = L
@@ -86,6 +87,11 @@ def lib():
 
 def _p(a, t=c_double_p):
     return a.ctypes.data_as(t) if a is not None else None
+
+
+def num_threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return lib().orc_num_threads()
 
 
 def dims(Q):

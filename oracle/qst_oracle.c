@@ -45,6 +45,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 /* ----------------------------------------------------------------------- */
 /* Philox4x64-10 (Salmon et al., SC'11): 10 rounds of the two-multiply      */
@@ -520,4 +521,16 @@ void orc_eval_batch(int Q, const int64_t* counts, int64_t n, const double* xs,
         free(packed);
         free(p);
     }
+}
+
+/* Threads an OpenMP parallel region of the oracle uses. */
+int orc_num_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
 }

@@ -85,13 +85,17 @@ struct TeamShape {
     using Dm = Dims<Q>;
     static_assert(G >= Dm::D, "a team must hold one D-lane transform group");
     static_assert(G <= 64 ? (64 % G == 0) : (G % 64 == 0), "team size must tile wavefronts");
-    static constexpr int NBL = (Dm::NB + G - 1) / G;      // normal blocks per lane
     static constexpr int NJL = (Dm::NB + 1 + G - 1) / G;  // Philox jobs per lane (normals + MH uniform)
-    static constexpr int NPL = (Dm::D2 + G - 1) / G;      // packed rho entries per lane
+    static constexpr int NYL = (Dm::d + G - 1) / G;       // state entries per lane (strided)
+    static constexpr int NPL = (Dm::D2 + G - 1) / G;      // packed rho entries per lane (strided)
     static constexpr int NFL = (Dm::KD + G - 1) / G;      // projector outputs per lane
     static constexpr int kMisc = 24;                      // per-team scratch doubles
-    // per-team LDS: y' / Pauli coefficients, column weights, packed rho', scratch
-    static constexpr int kLds = Dm::d + Dm::D + Dm::D2 + kMisc;
+    // per-team LDS (doubles): y' | Pauli coefficients | packed rho' | column weights | scratch
+    static constexpr int kOffPauli = Dm::d;
+    static constexpr int kOffRho = kOffPauli + Dm::D2;
+    static constexpr int kOffWt = kOffRho + Dm::D2;
+    static constexpr int kOffMisc = kOffWt + Dm::D;
+    static constexpr int kLds = kOffMisc + kMisc;
 };
 
 // ---------------------------------------------------------------------------
@@ -141,11 +145,12 @@ __device__ __forceinline__ int team_or(int v, double* scratch, int lane)
 // stages on LDS
 // ---------------------------------------------------------------------------
 
-// Column weights and packed rho from the parameters in ybuf (x layout).
-// rp[e] receives packed entry lane + G e; the packed matrix also goes to rhoP.
+// Column weights and packed rho from the parameters in ybuf (x layout):
+// w_j = (v_j^2 / sum_k v_k^2) / |z_j|^2, then packed entry p = (a, b) is
+// sum_j w_j Re(z_aj conj z_bj) for a <= b and sum_j w_j Im(z_bj conj z_aj)
+// for a > b.
 template <int Q, int G>
-__device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double* rhoP,
-                                          double (&rp)[TeamShape<Q, G>::NPL], int lane)
+__device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double* rhoP, int lane)
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
@@ -167,15 +172,16 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
         wt[j] = (v * v / V) / nz;
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 1
     for (int e = 0; e < S::NPL; ++e) {
         const int p = lane + G * e;
-        double acc = 0.0;
         if (p < D2) {
             const int a = p / D, b = p % D;
             const int r = a <= b ? a : b;   // row of the upper-triangle element
             const int c = a <= b ? b : a;
             const bool want_re = a <= b;
+            double acc = 0.0;
+#pragma unroll 4
             for (int j = 0; j < D; ++j) {
                 const double zr_r = ybuf[j * D + r], zi_r = ybuf[D2 + j * D + r];
                 const double zr_c = ybuf[j * D + c], zi_c = ybuf[D2 + j * D + c];
@@ -186,7 +192,6 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
             }
             rhoP[p] = acc;
         }
-        rp[e] = acc;
     }
 }
 
@@ -283,34 +288,50 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
     const bool live = chain < A.R;
     const int64_t c = live ? chain : 0;
 
-    double* ybuf = lds + team * S::kLds;
-    double* wt = ybuf + d;
-    double* rhoP = wt + Dm::D;
-    double* misc = rhoP + D2;
-    double* pauli = ybuf;  // reuses the parameter buffer once rho is built
+    double* base = lds + team * S::kLds;
+    double* ybuf = base;                 // proposal y' (x layout), kept until the decision
+    double* pauli = base + S::kOffPauli;
+    double* rhoP = base + S::kOffRho;
+    double* wt = base + S::kOffWt;
+    double* misc = base + S::kOffMisc;
 
-    double y[S::NBL * 4];
-    double yp[S::NBL * 4];
-    double rc[S::NPL], rp[S::NPL], s1[S::NPL], s2[S::NPL];
+    // registers: state entries i = lane + G e, packed-rho entries p = lane + G e
+    double y[S::NYL];
+    double rc[S::NPL], s1[S::NPL], s2[S::NPL];
     double ll, beta;
     int acc_w;
     int64_t nst, nacc = 0, nnear = 0;
 
-    // evaluate log L at the parameters in yp (team-uniform result)
-    auto evaluate = [&]() -> double {
-#pragma unroll
-        for (int e = 0; e < S::NBL; ++e) {
-            const int b = lane + G * e;
-            if (b < NB) {
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    const int i = 4 * b + w;
-                    if (i < d) ybuf[i] = yp[4 * e + w];
+    // Philox jobs of one step: normal block b -> eta[4b..4b+3] into ybuf,
+    // job NB -> the Metropolis-Hastings uniform into misc[0]
+    auto draw = [&](uint64_t step) {
+#pragma unroll 1
+        for (int e = 0; e < S::NJL; ++e) {
+            const int job = lane + G * e;
+            const bool normal = job < NB;
+            if (job <= NB) {
+                const uint64_t c0 = normal ? static_cast<uint64_t>(job) : 0;
+                const uint64_t c3 = normal ? 0 : (static_cast<uint64_t>(kTagMH) << 56);
+                const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(c), c3, A.seed, 0);
+                if (normal) {
+                    double n0, n1, n2, n3;
+                    box_muller(B.w[0], B.w[1], n0, n1);
+                    box_muller(B.w[2], B.w[3], n2, n3);
+                    const int i = 4 * job;
+                    ybuf[i] = n0;
+                    if (i + 1 < d) ybuf[i + 1] = n1;
+                    if (i + 2 < d) ybuf[i + 2] = n2;
+                    if (i + 3 < d) ybuf[i + 3] = n3;
+                } else {
+                    misc[0] = uniform_open(B.w[0]);
                 }
             }
         }
-        __syncthreads();
-        stage_rho<Q, G>(ybuf, wt, rhoP, rp, lane);
+    };
+
+    // log L at the parameters in ybuf (team-uniform result); leaves packed rho in rhoP
+    auto evaluate = [&]() -> double {
+        stage_rho<Q, G>(ybuf, wt, rhoP, lane);
         __syncthreads();
         stage_pauli<Q, G>(rhoP, pauli, lane);
         __syncthreads();
@@ -322,43 +343,20 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
         return anybad ? -INFINITY : tot;
     };
 
-    // Philox jobs of a step: normal blocks 0..NB-1, then the MH uniform (job NB)
-    auto draw = [&](uint64_t step, double a, double bt, bool initial) {
-#pragma unroll
-        for (int e = 0; e < S::NJL; ++e) {
-            const int job = lane + G * e;
-            const bool normal = job < NB;
-            const uint64_t c0 = normal ? static_cast<uint64_t>(job) : 0;
-            const uint64_t c3 = normal ? 0 : (static_cast<uint64_t>(kTagMH) << 56);
-            if (job <= NB) {
-                const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(c), c3, A.seed, 0);
-                if (normal) {
-                    double n[4];
-                    box_muller(B.w[0], B.w[1], n[0], n[1]);
-                    box_muller(B.w[2], B.w[3], n[2], n[3]);
-                    if (e < S::NBL) {
-#pragma unroll
-                        for (int w = 0; w < 4; ++w)
-                            yp[4 * e + w] = initial ? n[w] : a * y[4 * e + w] + bt * n[w];
-                    }
-                } else {
-                    misc[0] = uniform_open(B.w[0]);
-                }
-            }
-        }
-    };
-
     // ---- load or initialise the chain state ----
     if (A.init) {
-#pragma unroll
-        for (int e = 0; e < S::NBL * 4; ++e) y[e] = 0.0;
-        draw(0, 0.0, 1.0, true);
+        draw(0);                         // y^0 ~ N(0, I): Algorithm 2, first line
+        __syncthreads();
         ll = evaluate();
 #pragma unroll
-        for (int e = 0; e < S::NBL * 4; ++e) y[e] = yp[e];
+        for (int e = 0; e < S::NYL; ++e) {
+            const int i = lane + G * e;
+            y[e] = i < d ? ybuf[i] : 0.0;
+        }
 #pragma unroll
         for (int e = 0; e < S::NPL; ++e) {
-            rc[e] = rp[e];
+            const int p = lane + G * e;
+            rc[e] = p < D2 ? rhoP[p] : 0.0;
             s1[e] = 0.0;
             s2[e] = 0.0;
         }
@@ -368,13 +366,9 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
         __syncthreads();
     } else {
 #pragma unroll
-        for (int e = 0; e < S::NBL; ++e) {
-            const int b = lane + G * e;
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const int i = 4 * b + w;
-                y[4 * e + w] = (b < NB && i < d) ? A.x[c * d + i] : 0.0;
-            }
+        for (int e = 0; e < S::NYL; ++e) {
+            const int i = lane + G * e;
+            y[e] = i < d ? A.x[c * d + i] : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < S::NPL; ++e) {
@@ -396,7 +390,15 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
     for (int64_t t = 0; t < A.n_steps; ++t) {
         const int64_t j = A.step_begin + 1 + t;
         const double a = sqrt(1.0 - beta * beta);
-        draw(static_cast<uint64_t>(j), a, beta, false);
+        draw(static_cast<uint64_t>(j));
+        __syncthreads();
+        // pCN proposal y' = sqrt(1 - beta^2) y + beta eta, in place over eta
+#pragma unroll
+        for (int e = 0; e < S::NYL; ++e) {
+            const int i = lane + G * e;
+            if (i < d) ybuf[i] = a * y[e] + beta * ybuf[i];
+        }
+        __syncthreads();
         const double llp = evaluate();
         const double logu = log(misc[0]);
         const double delta = llp - ll;
@@ -404,9 +406,15 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
         nnear += fabs(logu - delta) < 1e-8 ? 1 : 0;
         if (accept) {
 #pragma unroll
-            for (int e = 0; e < S::NBL * 4; ++e) y[e] = yp[e];
+            for (int e = 0; e < S::NYL; ++e) {
+                const int i = lane + G * e;
+                if (i < d) y[e] = ybuf[i];
+            }
 #pragma unroll
-            for (int e = 0; e < S::NPL; ++e) rc[e] = rp[e];
+            for (int e = 0; e < S::NPL; ++e) {
+                const int p = lane + G * e;
+                if (p < D2) rc[e] = rhoP[p];
+            }
             ll = llp;
             ++acc_w;
             ++nacc;
@@ -448,13 +456,9 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
     // ---- write the state back ----
     if (live) {
 #pragma unroll
-        for (int e = 0; e < S::NBL; ++e) {
-            const int b = lane + G * e;
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const int i = 4 * b + w;
-                if (b < NB && i < d) A.x[c * d + i] = y[4 * e + w];
-            }
+        for (int e = 0; e < S::NYL; ++e) {
+            const int i = lane + G * e;
+            if (i < d) A.x[c * d + i] = y[e];
         }
 #pragma unroll
         for (int e = 0; e < S::NPL; ++e) {
@@ -477,7 +481,10 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
 }
 
 template <int Q, int G, int WG>
-__global__ __launch_bounds__(WG) void k_chains(ChainArgs A)
+#ifndef QST_CHAIN_MIN_WAVES
+#define QST_CHAIN_MIN_WAVES 4
+#endif
+__global__ __launch_bounds__(WG, (WG <= 64 ? QST_CHAIN_MIN_WAVES : 1)) void k_chains(ChainArgs A)
 {
     extern __shared__ double lds[];
     chain_tile<Q, G, WG>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds);
@@ -497,9 +504,10 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * (WG / G) + team;
     const bool live = idx < n;
     const int64_t c = live ? idx : 0;
-    double* pauli = lds + team * S::kLds;
-    double* rhoP = pauli + Dm::d + D;
-    double* misc = rhoP + D2;
+    double* base = lds + team * S::kLds;
+    double* pauli = base + S::kOffPauli;
+    double* rhoP = base + S::kOffRho;
+    double* misc = base + S::kOffMisc;
     for (int p = lane; p < D2; p += G) {
         const int a = p / D, b = p % D;
         // packed: Re rho_ab above/on the diagonal, Im rho_ba below it

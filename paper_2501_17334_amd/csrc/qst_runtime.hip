@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/qst.h"
+#include "acf_kernel.hpp"
 #include "chain_kernel.hpp"
 #include "pool_kernel.hpp"
 
@@ -469,14 +470,32 @@ qst_status qst_acf(const double* records, int64_t n_chains, int64_t n_samples, i
                    double* out, void* stream)
 {
     return guarded([&] {
-        (void)records;
-        (void)n_chains;
-        (void)n_samples;
-        (void)n_qubits;
-        (void)l_max;
-        (void)out;
-        (void)stream;
-        fail(QST_ERR_UNSUPPORTED, "qst_acf is not available in this build");
+        if (!records || !out) fail(QST_ERR_INVALID, "NULL buffer");
+        if (n_qubits < 1 || n_qubits > 6) fail(QST_ERR_INVALID, "n_qubits must be in 1..6");
+        if (n_chains < 1 || l_max < 0 || n_samples <= l_max)
+            fail(QST_ERR_INVALID, "need n_chains >= 1 and n_samples > l_max >= 0");
+        if (n_chains > 65535) fail(QST_ERR_INVALID, "at most 65535 recorded chains");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int D = 1 << n_qubits;
+        double* part = dev_alloc<double>(static_cast<size_t>(n_chains) * (l_max + 1));
+        double* outd = nullptr;
+        try {
+            outd = dev_alloc<double>(l_max + 1);
+            const dim3 grid((l_max + 1 + qst::kAcfLags - 1) / qst::kAcfLags, static_cast<unsigned>(n_chains));
+            hipLaunchKernelGGL(qst::k_acf_partial, grid, dim3(qst::kAcfThreads), 0, s, records, n_samples, D, l_max,
+                               part);
+            hip_check(hipGetLastError(), "acf launch");
+            hipLaunchKernelGGL(qst::k_acf_final, dim3(1), dim3(qst::kAcfThreads), 0, s, part, n_chains, l_max, outd);
+            hip_check(hipGetLastError(), "acf final launch");
+            hip_check(hipStreamSynchronize(s), "acf synchronize");
+            hip_check(hipMemcpy(out, outd, sizeof(double) * (l_max + 1), hipMemcpyDeviceToHost), "acf copy");
+        } catch (...) {
+            dev_free(part);
+            dev_free(outd);
+            throw;
+        }
+        dev_free(part);
+        dev_free(outd);
     });
 }
 

@@ -211,5 +211,21 @@ class Problem:
                                 stream if stream is not None else current_stream()))
 
 
+def acf(records_dev, l_max=200, stream=None):
+    """qst_acf: pooled c[0..l_max] (Eq. (ACFrho)) of recorded packed samples,
+    a torch device tensor [chains, N, D, D] float64."""
+    C_, N, D, _ = records_dev.shape
+    Q = int(D).bit_length() - 1
+    out = np.zeros(l_max + 1)
+    _check(lib().qst_acf(C.c_void_p(records_dev.data_ptr()), C_, N, Q, l_max, _f64(out),
+                         stream if stream is not None else current_stream()))
+    return out
+
+
+def iact(c):
+    """Eq. (IACT): tau = 1 + 2 sum_{l>=1} c[l]."""
+    return 1.0 + 2.0 * float(np.sum(c[1:]))
+
+
 def _run_desc(problem, cfg, trace, record, stream):
     return problem._run_desc(cfg, trace, record, stream)

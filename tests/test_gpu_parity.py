@@ -200,3 +200,15 @@ def test_invalid_run_arguments():
     with pytest.raises(qst.QstError) as e:
         P.run(qst.RunConfig(n_chains=4, n_steps=10, seed=1, resume=True))
     assert e.value.status == qst.QST_ERR_STATE
+
+
+def test_acf_matches_oracle_diagnostics():
+    from oracle import diagnostics as G
+    p = synth.make_problem("c2")
+    g = gpu_run(2, p.counts, n_chains=12, n_steps=3000, seed=3, beta0=0.05, adapt_every=100,
+                record_every=2, record_chains=10)
+    rec = g["records"]
+    want = G.acf(rec, l_max=60)
+    got = qst.acf(torch.from_numpy(rec).cuda(), l_max=60)
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+    assert got[0] == 1.0
