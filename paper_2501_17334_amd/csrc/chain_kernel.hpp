@@ -31,6 +31,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "fastmath.hpp"
 #include "rng.hpp"
 
 namespace qst {
@@ -97,6 +98,44 @@ struct TeamShape {
     static constexpr int kOffMisc = kOffWt + Dm::D;
     static constexpr int kLds = kOffMisc + kMisc;
 };
+
+// Per-workgroup tables at the start of LDS, ahead of the teams: the
+// logarithm breakpoints and, when it fits, the Pauli index mu(k, t) of every
+// (setting, transform position) pair.
+template <int Q>
+struct WgTables {
+    using Dm = Dims<Q>;
+    static constexpr bool kMuTable = Dm::KD * 2 <= 16384;
+    static constexpr int kLogDoubles = 2 * kLogTableSize;
+    static constexpr int kMuDoubles = kMuTable ? (Dm::KD * 2 + 7) / 8 : 0;
+    static constexpr int kDoubles = kLogDoubles + kMuDoubles;
+};
+
+// mu(k, t) = sum_q [t_q] (s_q(k) + 1) 4^(Q-1-q): the Pauli string whose
+// coefficient enters position t of setting k's Walsh-Hadamard transform.
+template <int Q>
+__device__ __forceinline__ int pauli_index(int k, int t)
+{
+    int mu = 0, kk = k;
+#pragma unroll
+    for (int q = Q - 1; q >= 0; --q) {
+        const int s = kk % 3;
+        kk /= 3;
+        if ((t >> (Q - 1 - q)) & 1) mu += (s + 1) << (2 * (Q - 1 - q));
+    }
+    return mu;
+}
+
+template <int Q>
+__device__ __forceinline__ void wg_tables_init(double* lds, int tid, int nthreads)
+{
+    using Dm = Dims<Q>;
+    log_table_init(reinterpret_cast<LogEntry*>(lds), tid, nthreads);
+    if constexpr (WgTables<Q>::kMuTable) {
+        uint16_t* mu = reinterpret_cast<uint16_t*>(lds + WgTables<Q>::kLogDoubles);
+        for (int f = tid; f < Dm::KD; f += nthreads) mu[f] = static_cast<uint16_t>(pauli_index<Q>(f / Dm::D, f % Dm::D));
+    }
+}
 
 // ---------------------------------------------------------------------------
 // team collectives (deterministic: every lane ends with the same bits)
@@ -232,41 +271,48 @@ __device__ __forceinline__ void stage_pauli(const double* rhoP, double* pauli, i
 }
 
 // Probabilities of every projector by a 2^Q-point Walsh-Hadamard transform
-// per setting across lanes, and the partial sum of c log p of this lane.
+// per setting across lanes, and this lane's share of sum c log p, kept as
+// (sum c e, sum c frac) with log p = e ln2 + frac.
 template <int Q, int G>
 __device__ __forceinline__ void stage_loglik(const double* pauli, const double* __restrict__ nd,
-                                             int lane, double& part, int& bad)
+                                             const double* tables, int lane, double& part_e,
+                                             double& part_f, int& bad)
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
     constexpr int D = Dm::D, KD = Dm::KD;
+    const LogEntry* tab = reinterpret_cast<const LogEntry*>(tables);
+    const uint16_t* mutab = reinterpret_cast<const uint16_t*>(tables + WgTables<Q>::kLogDoubles);
     const int i = lane & (D - 1);  // position inside the D-lane group (= outcome l)
-#pragma unroll 2
+#pragma unroll 1
     for (int e = 0; e < S::NFL; ++e) {
         const int f = lane + G * e;
-        const bool valid = f < KD;
-        const int k = valid ? f / D : 0;
-        int mu = 0, kk = k;
-#pragma unroll
-        for (int q = Q - 1; q >= 0; --q) {
-            const int s = kk % 3;
-            kk /= 3;
-            if ((i >> (Q - 1 - q)) & 1) mu += (s + 1) << (2 * (Q - 1 - q));
-        }
-        double val = valid ? pauli[mu] : 0.0;
+        const bool valid = (S::NFL * G == KD) || f < KD;
+        int mu;
+        if constexpr (WgTables<Q>::kMuTable) mu = valid ? mutab[f] : 0;
+        else mu = valid ? pauli_index<Q>(f / D, i) : 0;
+        double val = pauli[mu];
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
-            const double other = __shfl_xor(val, 1 << s, 64);
+            double other;
+            switch (s) {
+                case 0: other = xor_lane<1>(val); break;
+                case 1: other = xor_lane<2>(val); break;
+                case 2: other = xor_lane<4>(val); break;
+                case 3: other = xor_lane<8>(val); break;
+                case 4: other = xor_lane<16>(val); break;
+                default: other = xor_lane<32>(val); break;
+            }
             val = ((i >> s) & 1) ? other - val : val + other;
         }
         const double p = val * (1.0 / D);
-        if (valid) {
-            const double n = nd[f];
-            if (n > 0.0) {
-                if (p > 0.0) part += n * log(p);
-                else bad = 1;
-            }
-        }
+        const double n = valid ? nd[f] : 0.0;
+        const bool pos = p > 0.0;
+        bad |= (n > 0.0 && !pos) ? 1 : 0;
+        int ex;
+        const double fr = log_parts(pos ? p : 1.0, tab, ex);
+        part_e = __builtin_fma(n, static_cast<double>(ex), part_e);
+        part_f = __builtin_fma(n, fr, part_f);
     }
 }
 
@@ -274,7 +320,7 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
 // the chain tile
 // ---------------------------------------------------------------------------
 template <int Q, int G, int WG>
-__device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
+__device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tables, double* lds)
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
@@ -288,6 +334,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
     const bool live = chain < A.R;
     const int64_t c = live ? chain : 0;
 
+    const LogEntry* logtab = reinterpret_cast<const LogEntry*>(tables);
     double* base = lds + team * S::kLds;
     double* ybuf = base;                 // proposal y' (x layout), kept until the decision
     double* pauli = base + S::kOffPauli;
@@ -315,8 +362,8 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
                 const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(c), c3, A.seed, 0);
                 if (normal) {
                     double n0, n1, n2, n3;
-                    box_muller(B.w[0], B.w[1], n0, n1);
-                    box_muller(B.w[2], B.w[3], n2, n3);
+                    box_muller(B.w[0], B.w[1], n0, n1, logtab);
+                    box_muller(B.w[2], B.w[3], n2, n3, logtab);
                     const int i = 4 * job;
                     ybuf[i] = n0;
                     if (i + 1 < d) ybuf[i + 1] = n1;
@@ -335,12 +382,13 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
         __syncthreads();
         stage_pauli<Q, G>(rhoP, pauli, lane);
         __syncthreads();
-        double part = 0.0;
+        double part_e = 0.0, part_f = 0.0;
         int bad = 0;
-        stage_loglik<Q, G>(pauli, A.nd, lane, part, bad);
-        const double tot = team_sum<G>(part, misc + 4, lane);
+        stage_loglik<Q, G>(pauli, A.nd, tables, lane, part_e, part_f, bad);
+        const double tot_e = team_sum<G>(part_e, misc + 4, lane);
+        const double tot_f = team_sum<G>(part_f, misc + 4, lane);
         const int anybad = team_or<G>(bad, misc + 4, lane);
-        return anybad ? -INFINITY : tot;
+        return anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
     };
 
     // ---- load or initialise the chain state ----
@@ -400,7 +448,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* lds)
         }
         __syncthreads();
         const double llp = evaluate();
-        const double logu = log(misc[0]);
+        const double logu = fast_log(misc[0], logtab);
         const double delta = llp - ll;
         const bool accept = logu < delta;
         nnear += fabs(logu - delta) < 1e-8 ? 1 : 0;
@@ -487,7 +535,9 @@ template <int Q, int G, int WG>
 __global__ __launch_bounds__(WG, (WG <= 64 ? QST_CHAIN_MIN_WAVES : 1)) void k_chains(ChainArgs A)
 {
     extern __shared__ double lds[];
-    chain_tile<Q, G, WG>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds);
+    wg_tables_init<Q>(lds, threadIdx.x, WG);
+    __syncthreads();
+    chain_tile<Q, G, WG>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds, lds + WgTables<Q>::kDoubles);
 }
 
 // Eq. (likelihood) for n given density matrices (complex, interleaved,
@@ -499,7 +549,10 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
     constexpr int D = Dm::D, D2 = Dm::D2;
-    extern __shared__ double lds[];
+    extern __shared__ double lds_all[];
+    wg_tables_init<Q>(lds_all, threadIdx.x, WG);
+    double* tables = lds_all;
+    double* lds = lds_all + WgTables<Q>::kDoubles;
     const int tid = threadIdx.x, team = tid / G, lane = tid % G;
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * (WG / G) + team;
     const bool live = idx < n;
@@ -516,12 +569,13 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
     __syncthreads();
     stage_pauli<Q, G>(rhoP, pauli, lane);
     __syncthreads();
-    double part = 0.0;
+    double part_e = 0.0, part_f = 0.0;
     int bad = 0;
-    stage_loglik<Q, G>(pauli, nd, lane, part, bad);
-    const double tot = team_sum<G>(part, misc + 4, lane);
+    stage_loglik<Q, G>(pauli, nd, tables, lane, part_e, part_f, bad);
+    const double tot_e = team_sum<G>(part_e, misc + 4, lane);
+    const double tot_f = team_sum<G>(part_f, misc + 4, lane);
     const int anybad = team_or<G>(bad, misc + 4, lane);
-    if (live && lane == 0) ll_out[idx] = anybad ? -INFINITY : tot;
+    if (live && lane == 0) ll_out[idx] = anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
 }
 
 }  // namespace qst

@@ -103,7 +103,7 @@ void launch_chains_t(const qst::ChainArgs& a, hipStream_t s)
     using S = qst::TeamShape<Q, G>;
     const int64_t teams = WG / G;
     const int64_t blocks = (a.R + teams - 1) / teams;
-    const size_t lds = static_cast<size_t>(teams) * S::kLds * sizeof(double);
+    const size_t lds = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q>::kDoubles) * sizeof(double);
     static bool attr_done = false;
     if (!attr_done) {
         hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG>),
@@ -122,7 +122,7 @@ void launch_loglik_t(const double* nd, const double* rho, int64_t n, double* out
     using S = qst::TeamShape<Q, G>;
     const int64_t teams = WG / G;
     const int64_t blocks = (n + teams - 1) / teams;
-    const size_t lds = static_cast<size_t>(teams) * S::kLds * sizeof(double);
+    const size_t lds = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q>::kDoubles) * sizeof(double);
     static bool attr_done = false;
     if (!attr_done) {
         hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_loglik<Q, G, WG>),

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fastmath.hpp"
+
 namespace qst {
 
 constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ULL;
@@ -71,14 +73,16 @@ __device__ __forceinline__ double uniform_open(uint64_t w)
 }
 
 // Box-Muller (1958) on one pair of words: r = sqrt(-2 ln u_a),
-// theta = 2 pi u_b -> (r cos theta, r sin theta).
-__device__ __forceinline__ void box_muller(uint64_t wa, uint64_t wb, double& n0, double& n1)
+// theta = 2 pi u_b -> (r cos theta, r sin theta); ln from the table-driven
+// logarithm, sin/cos(2 pi u_b) as sin/cos(pi x) with x = 2 u_b in (0, 2).
+__device__ __forceinline__ void box_muller(uint64_t wa, uint64_t wb, double& n0, double& n1,
+                                           const LogEntry* __restrict__ logtab)
 {
     const double ua = uniform_open(wa);
     const double ub = uniform_open(wb);
-    const double r = sqrt(-2.0 * log(ua));
+    const double r = sqrt(-2.0 * fast_log(ua, logtab));
     double s, c;
-    sincos(2.0 * M_PI * ub, &s, &c);
+    sincospi_0_2(2.0 * ub, s, c);
     n0 = r * c;
     n1 = r * s;
 }
