@@ -184,15 +184,27 @@ __device__ __forceinline__ int team_or(int v, double* scratch, int lane)
 // stages on LDS
 // ---------------------------------------------------------------------------
 
-// Column weights and packed rho from the parameters in ybuf (x layout):
-// w_j = (v_j^2 / sum_k v_k^2) / |z_j|^2, then packed entry p = (a, b) is
-// sum_j w_j Re(z_aj conj z_bj) for a <= b and sum_j w_j Im(z_bj conj z_aj)
-// for a > b.
+// The packed-rho entries a lane owns: p = lane + G e, except on the MFMA
+// path (D = 16, one wavefront per chain), where a lane owns the four entries
+// of the 16x16x4 FP64 MFMA result layout: row lane / 16 + 4 e, column lane % 16.
 template <int Q, int G>
-__device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double* rhoP, int lane)
+struct RhoLayout {
+    static constexpr bool kMfma = (Q == 4 && G == 64);
+};
+
+template <int Q, int G>
+__device__ __forceinline__ int packed_slot(int lane, int e)
+{
+    if constexpr (RhoLayout<Q, G>::kMfma) return ((lane >> 4) + 4 * e) * 16 + (lane & 15);
+    else return lane + G * e;
+}
+
+// Column weights w_j = (v_j^2 / sum_k v_k^2) / |z_j|^2 from the parameters in
+// ybuf (x layout); the MFMA path stores sqrt(w_j) instead.
+template <int Q, int G, bool kSqrt>
+__device__ __forceinline__ void stage_weights(const double* ybuf, double* wt, int lane)
 {
     using Dm = Dims<Q>;
-    using S = TeamShape<Q, G>;
     constexpr int D = Dm::D, D2 = Dm::D2;
     double V = 0.0;
 #pragma unroll 4
@@ -208,65 +220,137 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
             nz += re * re + im * im;
         }
         const double v = ybuf[2 * D2 + j];
-        wt[j] = (v * v / V) / nz;
+        const double w = (v * v / V) / nz;
+        wt[j] = kSqrt ? sqrt(w) : w;
     }
-    __syncthreads();
+}
+
+// Packed rho = sum_j w_j z_j z_j^dag into rhoP (LDS) and rp (this lane's
+// slots): entry (a, b) is sum_j w_j Re(z_aj conj z_bj) for a <= b and
+// sum_j w_j Im(z_bj conj z_aj) for a > b.
+template <int Q, int G>
+__device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double* rhoP,
+                                          double (&rp)[TeamShape<Q, G>::NPL], int lane)
+{
+    using Dm = Dims<Q>;
+    using S = TeamShape<Q, G>;
+    constexpr int D = Dm::D, D2 = Dm::D2;
+    if constexpr (RhoLayout<Q, G>::kMfma) {
+        // rho = Zs Zs^dag with Zs = Z diag(sqrt w): Re rho = Zr Zr^T + Zi Zi^T and
+        // Im rho = Zi Zr^T - Zr Zi^T, i.e. two 16x16 real products with K = 32,
+        // eight v_mfma_f64_16x16x4f64 each.  Operand lane l carries
+        // A[l % 16][k0 + l / 16]; for a Gram product the B operand is the same value.
+        stage_weights<Q, G, true>(ybuf, wt, lane);
+        __syncthreads();
+        typedef double double4_t __attribute__((ext_vector_type(4)));
+        double4_t re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+        const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j = 4 * t + kq;
+            const double sj = wt[j];
+            const double zr = ybuf[j * D + i] * sj;
+            const double zi = ybuf[D2 + j * D + i] * sj;
+            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zr, zr, re, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zi, zi, re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f64_16x16x4f64(zi, zr, im, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f64_16x16x4f64(-zr, zi, im, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = kq + 4 * e, col = i;   // result register e of lane l: row l/16 + 4e
+            const double v = row <= col ? re[e] : -im[e];   // P[a][b] = Im rho_ba = -Im rho_ab below
+            rp[e] = v;
+            rhoP[row * 16 + col] = v;
+        }
+    } else {
+        stage_weights<Q, G, false>(ybuf, wt, lane);
+        __syncthreads();
 #pragma unroll 1
-    for (int e = 0; e < S::NPL; ++e) {
-        const int p = lane + G * e;
-        if (p < D2) {
-            const int a = p / D, b = p % D;
-            const int r = a <= b ? a : b;   // row of the upper-triangle element
-            const int c = a <= b ? b : a;
-            const bool want_re = a <= b;
+        for (int e = 0; e < S::NPL; ++e) {
+            const int p = lane + G * e;
             double acc = 0.0;
+            if (p < D2) {
+                const int a = p / D, b = p % D;
+                const int r = a <= b ? a : b;   // row of the upper-triangle element
+                const int c = a <= b ? b : a;
+                const bool want_re = a <= b;
 #pragma unroll 4
-            for (int j = 0; j < D; ++j) {
-                const double zr_r = ybuf[j * D + r], zi_r = ybuf[D2 + j * D + r];
-                const double zr_c = ybuf[j * D + c], zi_c = ybuf[D2 + j * D + c];
-                // z_r conj(z_c): real part and imaginary part
-                const double re = zr_r * zr_c + zi_r * zi_c;
-                const double im = zi_r * zr_c - zr_r * zi_c;
-                acc += wt[j] * (want_re ? re : im);
+                for (int j = 0; j < D; ++j) {
+                    const double zr_r = ybuf[j * D + r], zi_r = ybuf[D2 + j * D + r];
+                    const double zr_c = ybuf[j * D + c], zi_c = ybuf[D2 + j * D + c];
+                    // z_r conj(z_c): real part and imaginary part
+                    const double re = zr_r * zr_c + zi_r * zi_c;
+                    const double im = zi_r * zr_c - zr_r * zi_c;
+                    acc += wt[j] * (want_re ? re : im);
+                }
+                rhoP[p] = acc;
             }
-            rhoP[p] = acc;
+            rp[e] = acc;
         }
     }
 }
 
 // Pauli coefficients c_mu = Tr(rho sigma_mu), mu = sum_q mu_q 4^(Q-1-q) with
-// mu_q in {I=0, X=1, Y=2, Z=3}.  (sigma_mu)_{a^m, a} = i^nY (-1)^popcount(a & zy)
-// where m marks X/Y qubits and zy marks Z/Y qubits, so
-// c_mu = Re[i^nY sum_a (-1)^popcount(a&zy) rho_{a, a^m}].
+// mu_q in {I=0, X=1, Y=2, Z=3}.  sigma_mu has one non-zero per row:
+// (sigma_mu)_{a^m, a} = i^nY (-1)^popcount(a & zy), with m marking the X/Y
+// qubits, zy the Z/Y qubits and nY = popcount(m & zy).  For one flip mask m,
+// the coefficients of all 2^Q masks zy are therefore a Walsh-Hadamard
+// transform over a of the generalised diagonal v_m[a] = rho_{a, a^m}:
+// c = Re(i^nY W_m[zy]).  Lanes hold (m, a), butterflies run across the D-lane
+// group, and lane position a ends holding zy = a.
+__device__ __forceinline__ int spread_bits(int x)   // bit q -> bit 2q (x < 256)
+{
+    x = (x | (x << 4)) & 0x0F0F;
+    x = (x | (x << 2)) & 0x3333;
+    x = (x | (x << 1)) & 0x5555;
+    return x;
+}
+
+template <int Q>
+__device__ __forceinline__ double xor_lane_stage(double v, int s)
+{
+    switch (s) {
+        case 0: return xor_lane<1>(v);
+        case 1: return xor_lane<2>(v);
+        case 2: return xor_lane<4>(v);
+        case 3: return xor_lane<8>(v);
+        case 4: return xor_lane<16>(v);
+        default: return xor_lane<32>(v);
+    }
+}
+
 template <int Q, int G>
 __device__ __forceinline__ void stage_pauli(const double* rhoP, double* pauli, int lane)
 {
     using Dm = Dims<Q>;
     constexpr int D = Dm::D, D2 = Dm::D2;
-    for (int mu = lane; mu < D2; mu += G) {
-        int m = 0, zy = 0, nY = 0;
+    constexpr int NPASS = (D2 + G - 1) / G;
+    const int a = lane & (D - 1);
+#pragma unroll 1
+    for (int e = 0; e < NPASS; ++e) {
+        const int item = lane + G * e;          // item = m D + a
+        const bool valid = (NPASS * G == D2) || item < D2;
+        const int m = valid ? (item >> Q) : 0;
+        const int b = a ^ m;
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        double re = rhoP[lo * D + hi];
+        const double pim = rhoP[hi * D + lo];   // Im of the upper element (a != b)
+        double im = (a == b) ? 0.0 : (a < b ? pim : -pim);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int dig = (mu >> (2 * (Q - 1 - q))) & 3;
-            const int bit = 1 << (Q - 1 - q);
-            if (dig == 1 || dig == 2) m |= bit;
-            if (dig == 2 || dig == 3) zy |= bit;
-            nY += (dig == 2);
+        for (int s = 0; s < Q; ++s) {
+            const double ore = xor_lane_stage<Q>(re, s);
+            const double oim = xor_lane_stage<Q>(im, s);
+            const bool up = (a >> s) & 1;
+            re = up ? ore - re : re + ore;
+            im = up ? oim - im : im + oim;
         }
-        const bool odd = nY & 1;
-        double s = 0.0;
-        for (int a = 0; a < D; ++a) {
-            const int b = a ^ m;
-            const int lo = a < b ? a : b, hi = a < b ? b : a;
-            // even nY: Re rho_ab = P[lo][hi]; odd nY: Im rho_ab = +-P[hi][lo] (a != b)
-            const int idx = odd ? hi * D + lo : lo * D + hi;
-            const double sgn_im = (odd && a > b) ? -1.0 : 1.0;
-            const double sgn_z = (__popc(a & zy) & 1) ? -1.0 : 1.0;
-            s += (sgn_z * sgn_im) * rhoP[idx];
-        }
-        // i^nY: nY%4 = 0 -> +Re S, 1 -> -Im S, 2 -> -Re S, 3 -> +Im S
-        const int r4 = nY & 3;
-        pauli[mu] = (r4 == 1 || r4 == 2) ? -s : s;
+        const int zy = a;
+        const int r4 = __popc(m & zy) & 3;
+        const double c = r4 == 0 ? re : (r4 == 1 ? -im : (r4 == 2 ? -re : im));
+        // digit (m_q, zy_q): (0,0) -> I, (1,0) -> X, (1,1) -> Y, (0,1) -> Z
+        const int mu = (spread_bits(zy) << 1) | spread_bits(m ^ zy);
+        if (valid) pauli[mu] = c;
     }
 }
 
@@ -294,15 +378,7 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
         double val = pauli[mu];
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
-            double other;
-            switch (s) {
-                case 0: other = xor_lane<1>(val); break;
-                case 1: other = xor_lane<2>(val); break;
-                case 2: other = xor_lane<4>(val); break;
-                case 3: other = xor_lane<8>(val); break;
-                case 4: other = xor_lane<16>(val); break;
-                default: other = xor_lane<32>(val); break;
-            }
+            const double other = xor_lane_stage<Q>(val, s);
             val = ((i >> s) & 1) ? other - val : val + other;
         }
         const double p = val * (1.0 / D);
@@ -344,7 +420,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
 
     // registers: state entries i = lane + G e, packed-rho entries p = lane + G e
     double y[S::NYL];
-    double rc[S::NPL], s1[S::NPL], s2[S::NPL];
+    double rc[S::NPL], rp[S::NPL], s1[S::NPL], s2[S::NPL];
     double ll, beta;
     int acc_w;
     int64_t nst, nacc = 0, nnear = 0;
@@ -378,7 +454,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
 
     // log L at the parameters in ybuf (team-uniform result); leaves packed rho in rhoP
     auto evaluate = [&]() -> double {
-        stage_rho<Q, G>(ybuf, wt, rhoP, lane);
+        stage_rho<Q, G>(ybuf, wt, rhoP, rp, lane);
         __syncthreads();
         stage_pauli<Q, G>(rhoP, pauli, lane);
         __syncthreads();
@@ -403,8 +479,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
         }
 #pragma unroll
         for (int e = 0; e < S::NPL; ++e) {
-            const int p = lane + G * e;
-            rc[e] = p < D2 ? rhoP[p] : 0.0;
+            rc[e] = rp[e];
             s1[e] = 0.0;
             s2[e] = 0.0;
         }
@@ -420,7 +495,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
         }
 #pragma unroll
         for (int e = 0; e < S::NPL; ++e) {
-            const int p = lane + G * e;
+            const int p = packed_slot<Q, G>(lane, e);
             const bool ok = p < D2;
             rc[e] = ok ? A.rho_cur[c * D2 + p] : 0.0;
             s1[e] = ok ? A.s1[c * D2 + p] : 0.0;
@@ -459,10 +534,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
                 if (i < d) y[e] = ybuf[i];
             }
 #pragma unroll
-            for (int e = 0; e < S::NPL; ++e) {
-                const int p = lane + G * e;
-                if (p < D2) rc[e] = rhoP[p];
-            }
+            for (int e = 0; e < S::NPL; ++e) rc[e] = rp[e];
             ll = llp;
             ++acc_w;
             ++nacc;
@@ -494,7 +566,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
             double* dst = A.rec + (chain * n_rec + slot) * D2;
 #pragma unroll
             for (int e = 0; e < S::NPL; ++e) {
-                const int p = lane + G * e;
+                const int p = packed_slot<Q, G>(lane, e);
                 if (p < D2) dst[p] = rc[e];
             }
         }
@@ -510,7 +582,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
         }
 #pragma unroll
         for (int e = 0; e < S::NPL; ++e) {
-            const int p = lane + G * e;
+            const int p = packed_slot<Q, G>(lane, e);
             if (p < D2) {
                 A.rho_cur[c * D2 + p] = rc[e];
                 A.s1[c * D2 + p] = s1[e];
