@@ -51,6 +51,7 @@ struct Dims {
 // Everything a chain launch needs; plain pointers into the problem's buffers.
 struct ChainArgs {
     const double* nd;       // [KD] counts as doubles
+    const void* mfrag;      // dense path: the Pauli matrix in MFMA fragment order
     int64_t R;              // chains of the problem
     double* x;              // [R][d] current state
     double* ll;             // [R] log L of the current state
@@ -81,7 +82,29 @@ struct ChainArgs {
     double* rec;
 };
 
-template <int Q, int G>
+// How p = Tr(Lambda rho) is formed inside the chain step.
+enum : int { kPathKron = 0, kPathDense = 1 };
+// Arithmetic of the dense contraction (the log-likelihood sum is FP64 always).
+enum : int { kPrecF64 = 0, kPrecF32 = 1, kPrecBF16x3 = 2 };
+
+// Sizes of the dense contraction p = M vec(rho) for one workgroup of 16
+// chains: M is KD x D^2 (rows padded to 16 for the MFMA tiles, columns to
+// 32 for the BF16 k-steps).
+template <int Q>
+struct DenseShape {
+    static constexpr int KD = Dims<Q>::KD;
+    static constexpr int KDP = (KD + 15) / 16 * 16;
+    static constexpr int NT = KDP / 16;              // 16-row output tiles
+    static constexpr int K = Dims<Q>::D2;
+    static constexpr int KS4 = K / 4;                // k-steps of the 16x16x4 FP64/FP32 MFMA
+    static constexpr int KP32 = (K + 31) / 32 * 32;
+    static constexpr int KS32 = KP32 / 32;           // k-steps of the 16x16x32 BF16 MFMA
+    static constexpr int kChains = 16;               // MFMA N dimension = chains per workgroup
+    // B-operand staging per chain: FP32 copy or three BF16 parts (in doubles)
+    static constexpr int kStageDoubles = (6 * KP32 + 7) / 8;
+};
+
+template <int Q, int G, int PATH = kPathKron>
 struct TeamShape {
     using Dm = Dims<Q>;
     static_assert(G >= Dm::D, "a team must hold one D-lane transform group");
@@ -91,24 +114,33 @@ struct TeamShape {
     static constexpr int NPL = (Dm::D2 + G - 1) / G;      // packed rho entries per lane (strided)
     static constexpr int NFL = (Dm::KD + G - 1) / G;      // projector outputs per lane
     static constexpr int kMisc = 24;                      // per-team scratch doubles
+    // the Pauli-coefficient region doubles as the dense path's B-operand staging
+    static constexpr int kPauliDoubles =
+        PATH == kPathDense && DenseShape<Q>::kStageDoubles > Dm::D2 ? DenseShape<Q>::kStageDoubles : Dm::D2;
     // per-team LDS (doubles): y' | Pauli coefficients | packed rho' | column weights | scratch
     static constexpr int kOffPauli = Dm::d;
-    static constexpr int kOffRho = kOffPauli + Dm::D2;
+    static constexpr int kOffRho = kOffPauli + kPauliDoubles;
     static constexpr int kOffWt = kOffRho + Dm::D2;
     static constexpr int kOffMisc = kOffWt + Dm::D;
-    static constexpr int kLds = kOffMisc + kMisc;
+    static constexpr int kLdsRaw = kOffMisc + kMisc;
+    // dense path: 16 teams are read side by side; a stride of 16k+1 doubles
+    // keeps the 16 lanes of an MFMA column group on distinct LDS banks
+    static constexpr int kLds = PATH == kPathDense ? (kLdsRaw + 14) / 16 * 16 + 1 : kLdsRaw;
 };
 
 // Per-workgroup tables at the start of LDS, ahead of the teams: the
 // logarithm breakpoints and, when it fits, the Pauli index mu(k, t) of every
 // (setting, transform position) pair.
-template <int Q>
+template <int Q, int PATH = kPathKron>
 struct WgTables {
     using Dm = Dims<Q>;
-    static constexpr bool kMuTable = Dm::KD * 2 <= 16384;
+    static constexpr bool kMuTable = PATH == kPathKron && Dm::KD * 2 <= 16384;
     static constexpr int kLogDoubles = 2 * kLogTableSize;
     static constexpr int kMuDoubles = kMuTable ? (Dm::KD * 2 + 7) / 8 : 0;
-    static constexpr int kDoubles = kLogDoubles + kMuDoubles;
+    // dense path: per-wave partial log-likelihoods [16 waves][16 chains][3]
+    static constexpr int kRedDoubles = PATH == kPathDense ? 16 * 16 * 3 : 0;
+    static constexpr int kOffRed = kLogDoubles + kMuDoubles;
+    static constexpr int kDoubles = kOffRed + kRedDoubles;
 };
 
 // mu(k, t) = sum_q [t_q] (s_q(k) + 1) 4^(Q-1-q): the Pauli string whose
@@ -126,13 +158,13 @@ __device__ __forceinline__ int pauli_index(int k, int t)
     return mu;
 }
 
-template <int Q>
+template <int Q, int PATH = kPathKron>
 __device__ __forceinline__ void wg_tables_init(double* lds, int tid, int nthreads)
 {
     using Dm = Dims<Q>;
     log_table_init(reinterpret_cast<LogEntry*>(lds), tid, nthreads);
-    if constexpr (WgTables<Q>::kMuTable) {
-        uint16_t* mu = reinterpret_cast<uint16_t*>(lds + WgTables<Q>::kLogDoubles);
+    if constexpr (WgTables<Q, PATH>::kMuTable) {
+        uint16_t* mu = reinterpret_cast<uint16_t*>(lds + WgTables<Q, PATH>::kLogDoubles);
         for (int f = tid; f < Dm::KD; f += nthreads) mu[f] = static_cast<uint16_t>(pauli_index<Q>(f / Dm::D, f % Dm::D));
     }
 }
@@ -393,13 +425,165 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
 }
 
 // ---------------------------------------------------------------------------
+// dense contraction on MFMA: p = M vec(rho) for the 16 chains of a workgroup
+// ---------------------------------------------------------------------------
+// M (KD x D^2, exact entries 0 or +-2^-a in every precision) is stored in the
+// order the MFMA A operand is consumed: for output tile nt and k-step ks,
+// 64 lanes' fragments back to back (FP64/FP32: lane l holds M[16 nt + l%16]
+// [4 ks + l/16]; BF16: lane l holds M[16 nt + l%16][32 ks + 8 (l/16) + v],
+// v = 0..7).  The B operand is packed rho of chain l%16 at the same k, read
+// from that chain's team region in LDS.  Results: FP64 lane l register r is
+// row l/16 + 4r; FP32/BF16 lane l register r is row 4 (l/16) + r; the column
+// is the chain l % 16 in both.
+typedef double dense_f64x4 __attribute__((ext_vector_type(4)));
+typedef float dense_f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 dense_bf16x8 __attribute__((ext_vector_type(8)));
+
+// Reduced-precision B operands: the FP32 rounding of packed rho, or its
+// three-part BF16 split x = hi + mid + lo (each part the BF16 rounding of
+// what the previous parts leave), written into the team's staging region.
+template <int Q, int G, int PREC>
+__device__ __forceinline__ void stage_dense_operands(const double* rhoP, double* stage, int lane)
+{
+    using DS = DenseShape<Q>;
+    if constexpr (PREC == kPrecF32) {
+        float* f = reinterpret_cast<float*>(stage);
+        for (int k = lane; k < DS::K; k += G) f[k] = static_cast<float>(rhoP[k]);
+    } else if constexpr (PREC == kPrecBF16x3) {
+        __bf16* h = reinterpret_cast<__bf16*>(stage);
+        for (int k = lane; k < DS::KP32; k += G) {
+            const double x = k < DS::K ? rhoP[k] : 0.0;
+            const __bf16 hi = static_cast<__bf16>(static_cast<float>(x));
+            const double r1 = x - static_cast<double>(static_cast<float>(hi));
+            const __bf16 mid = static_cast<__bf16>(static_cast<float>(r1));
+            const double r2 = r1 - static_cast<double>(static_cast<float>(mid));
+            const __bf16 lo = static_cast<__bf16>(static_cast<float>(r2));
+            h[k] = hi;
+            h[DS::KP32 + k] = mid;
+            h[2 * DS::KP32 + k] = lo;
+        }
+    }
+}
+
+// Partial sums of c log p for the 16 chains of the workgroup; the calling
+// thread's wave covers output tiles wave, wave + nwaves, ...  Each lane keeps
+// the sums of its column chain (l % 16).
+template <int Q, int PREC, int NWAVES, int TEAM_LDS>
+__device__ __forceinline__ void dense_partials(const double* lds_teams, int off_rho, int off_stage,
+                                               const void* __restrict__ mfrag, const double* __restrict__ nd,
+                                               const LogEntry* logtab, int wave, int l, double& part_e,
+                                               double& part_f, int& bad)
+{
+    using DS = DenseShape<Q>;
+    const int col = l & 15, kq = l >> 4;
+    const double* team_base = lds_teams + col * TEAM_LDS;
+#pragma unroll 1
+    for (int nt = wave; nt < DS::NT; nt += NWAVES) {
+        double pr[4];
+        if constexpr (PREC == kPrecF64) {
+            const double* A = static_cast<const double*>(mfrag) + static_cast<size_t>(nt) * DS::KS4 * 64;
+            const double* B = team_base + off_rho;
+            dense_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int ks = 0; ks < DS::KS4; ++ks)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks * 64 + l], B[4 * ks + kq], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pr[r] = acc[r];
+        } else if constexpr (PREC == kPrecF32) {
+            const float* A = static_cast<const float*>(mfrag) + static_cast<size_t>(nt) * DS::KS4 * 64;
+            const float* B = reinterpret_cast<const float*>(team_base + off_stage);
+            dense_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+            for (int ks = 0; ks < DS::KS4; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks * 64 + l], B[4 * ks + kq], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pr[r] = static_cast<double>(acc[r]);
+        } else {
+            const dense_bf16x8* A = static_cast<const dense_bf16x8*>(mfrag) + static_cast<size_t>(nt) * DS::KS32 * 64;
+            const __bf16* B = reinterpret_cast<const __bf16*>(team_base + off_stage);
+            dense_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < DS::KS32; ++ks) {
+                const dense_bf16x8 a = A[ks * 64 + l];
+                const int k0 = 32 * ks + 8 * kq;
+#pragma unroll
+                for (int part = 0; part < 3; ++part) {
+                    const dense_bf16x8 b = *reinterpret_cast<const dense_bf16x8*>(B + part * DS::KP32 + k0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pr[r] = static_cast<double>(acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = PREC == kPrecF64 ? kq + 4 * r : 4 * kq + r;
+            const int kl = 16 * nt + row;
+            const double n = kl < DS::KD ? nd[kl] : 0.0;
+            double p = pr[r];
+            // reduced precision: a probability that rounds below the smallest
+            // normal FP32 value is taken at that value
+            if constexpr (PREC != kPrecF64) p = fmax(p, 0x1.0p-126);
+            const bool pos = p > 0.0;
+            bad |= (n > 0.0 && !pos) ? 1 : 0;
+            int ex;
+            const double fr = log_parts(pos ? p : 1.0, logtab, ex);
+            part_e = __builtin_fma(n, static_cast<double>(ex), part_e);
+            part_f = __builtin_fma(n, fr, part_f);
+        }
+    }
+    // fold the four row groups of each column (lanes l, l^16, l^32, l^48)
+    part_e += __shfl_xor(part_e, 16, 64);
+    part_f += __shfl_xor(part_f, 16, 64);
+    bad |= __shfl_xor(bad, 16, 64);
+    part_e += __shfl_xor(part_e, 32, 64);
+    part_f += __shfl_xor(part_f, 32, 64);
+    bad |= __shfl_xor(bad, 32, 64);
+}
+
+// log L of the 16 chains of a workgroup of 16 one-wave teams (G = 64);
+// returns the calling team's value.  All threads of the workgroup call it.
+template <int Q, int PREC>
+__device__ __forceinline__ double dense_loglik_wg(double* lds_teams, double* red, const void* mfrag,
+                                                  const double* nd, const LogEntry* logtab, int tid)
+{
+    using S = TeamShape<Q, 64, kPathDense>;
+    constexpr int NW = 16;
+    const int wave = tid >> 6, l = tid & 63;
+    stage_dense_operands<Q, 64, PREC>(lds_teams + wave * S::kLds + S::kOffRho, lds_teams + wave * S::kLds + S::kOffPauli,
+                                      l);
+    __syncthreads();
+    double pe = 0.0, pf = 0.0;
+    int bad = 0;
+    dense_partials<Q, PREC, NW, S::kLds>(lds_teams, S::kOffRho, S::kOffPauli, mfrag, nd, logtab, wave, l, pe, pf,
+                                         bad);
+    if (l < 16) {
+        red[(wave * 16 + l) * 3 + 0] = pe;
+        red[(wave * 16 + l) * 3 + 1] = pf;
+        red[(wave * 16 + l) * 3 + 2] = static_cast<double>(bad);
+    }
+    __syncthreads();
+    double te = 0.0, tf = 0.0;
+    int tb = 0;
+#pragma unroll 4
+    for (int w = 0; w < NW; ++w) {
+        te += red[(w * 16 + wave) * 3 + 0];
+        tf += red[(w * 16 + wave) * 3 + 1];
+        tb |= static_cast<int>(red[(w * 16 + wave) * 3 + 2]);
+    }
+    __syncthreads();
+    return tb ? -INFINITY : __builtin_fma(te, kLn2, tf);
+}
+
+// ---------------------------------------------------------------------------
 // the chain tile
 // ---------------------------------------------------------------------------
-template <int Q, int G, int WG>
+template <int Q, int G, int WG, int PATH, int PREC>
 __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tables, double* lds)
 {
     using Dm = Dims<Q>;
-    using S = TeamShape<Q, G>;
+    using S = TeamShape<Q, G, PATH>;
+    static_assert(PATH == kPathKron ? PREC == kPrecF64 : (G == 64 && WG == 1024), "unsupported path");
     constexpr int D2 = Dm::D2, d = Dm::d, NB = Dm::NB;
     static_assert(WG % G == 0, "workgroup must hold whole teams");
 
@@ -456,15 +640,19 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
     auto evaluate = [&]() -> double {
         stage_rho<Q, G>(ybuf, wt, rhoP, rp, lane);
         __syncthreads();
-        stage_pauli<Q, G>(rhoP, pauli, lane);
-        __syncthreads();
-        double part_e = 0.0, part_f = 0.0;
-        int bad = 0;
-        stage_loglik<Q, G>(pauli, A.nd, tables, lane, part_e, part_f, bad);
-        const double tot_e = team_sum<G>(part_e, misc + 4, lane);
-        const double tot_f = team_sum<G>(part_f, misc + 4, lane);
-        const int anybad = team_or<G>(bad, misc + 4, lane);
-        return anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
+        if constexpr (PATH == kPathDense) {
+            return dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, PATH>::kOffRed, A.mfrag, A.nd, logtab, tid);
+        } else {
+            stage_pauli<Q, G>(rhoP, pauli, lane);
+            __syncthreads();
+            double part_e = 0.0, part_f = 0.0;
+            int bad = 0;
+            stage_loglik<Q, G>(pauli, A.nd, tables, lane, part_e, part_f, bad);
+            const double tot_e = team_sum<G>(part_e, misc + 4, lane);
+            const double tot_f = team_sum<G>(part_f, misc + 4, lane);
+            const int anybad = team_or<G>(bad, misc + 4, lane);
+            return anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
+        }
     };
 
     // ---- load or initialise the chain state ----
@@ -600,16 +788,17 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
     }
 }
 
-template <int Q, int G, int WG>
 #ifndef QST_CHAIN_MIN_WAVES
 #define QST_CHAIN_MIN_WAVES 4
 #endif
+template <int Q, int G, int WG, int PATH = kPathKron, int PREC = kPrecF64>
 __global__ __launch_bounds__(WG, (WG <= 64 ? QST_CHAIN_MIN_WAVES : 1)) void k_chains(ChainArgs A)
 {
     extern __shared__ double lds[];
-    wg_tables_init<Q>(lds, threadIdx.x, WG);
+    wg_tables_init<Q, PATH>(lds, threadIdx.x, WG);
     __syncthreads();
-    chain_tile<Q, G, WG>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds, lds + WgTables<Q>::kDoubles);
+    chain_tile<Q, G, WG, PATH, PREC>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds,
+                                     lds + WgTables<Q, PATH>::kDoubles);
 }
 
 // Eq. (likelihood) for n given density matrices (complex, interleaved,
@@ -648,6 +837,34 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
     const double tot_f = team_sum<G>(part_f, misc + 4, lane);
     const int anybad = team_or<G>(bad, misc + 4, lane);
     if (live && lane == 0) ll_out[idx] = anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
+}
+
+// Dense-path Eq. (likelihood) for n given density matrices: 16 matrices per
+// workgroup of 16 waves.
+template <int Q, int PREC>
+__global__ __launch_bounds__(1024) void k_loglik_dense(const double* __restrict__ nd, const void* mfrag,
+                                                       const double* rho, int64_t n, double* ll_out)
+{
+    using Dm = Dims<Q>;
+    using S = TeamShape<Q, 64, kPathDense>;
+    constexpr int D = Dm::D, D2 = Dm::D2;
+    extern __shared__ double lds_all[];
+    wg_tables_init<Q, kPathDense>(lds_all, threadIdx.x, 1024);
+    double* tables = lds_all;
+    double* lds = lds_all + WgTables<Q, kPathDense>::kDoubles;
+    const int tid = threadIdx.x, team = tid >> 6, lane = tid & 63;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 16 + team;
+    const bool live = idx < n;
+    const int64_t c = live ? idx : 0;
+    double* rhoP = lds + team * S::kLds + S::kOffRho;
+    for (int p = lane; p < D2; p += 64) {
+        const int a = p / D, b = p % D;
+        rhoP[p] = a <= b ? rho[(c * D2 + a * D + b) * 2] : rho[(c * D2 + b * D + a) * 2 + 1];
+    }
+    __syncthreads();
+    const double ll = dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, kPathDense>::kOffRed, mfrag, nd,
+                                               reinterpret_cast<const LogEntry*>(tables), tid);
+    if (live && lane == 0) ll_out[idx] = ll;
 }
 
 }  // namespace qst

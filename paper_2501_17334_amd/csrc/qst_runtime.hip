@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -79,6 +80,86 @@ int ipow3(int q)
     return k;
 }
 
+// ---------------------------------------------------------------------------
+// The Pauli measurement matrix of the dense path, built exactly on the host.
+// Row kl = k D + l holds Tr(Lambda_kl rho) as a linear form of packed rho:
+// p = sum_a rho_aa Pi_aa + sum_{a<b} 2 (Re rho_ab Re Pi_ab + Im rho_ab Im Pi_ab)
+// with Pi = Lambda_kl = (x)_q pi_{s_q b_q}.  Every entry is 0 or +-2^-j, exact in
+// FP64, FP32 and BF16.
+// ---------------------------------------------------------------------------
+std::complex<double> qubit_projector(int s, int b, int x, int y)
+{
+    if (s == 2) return (x == b && y == b) ? 1.0 : 0.0;          // Z: |b><b|
+    const double sgn = b == 0 ? 1.0 : -1.0;                     // b = 0: eigenvalue +1
+    if (x == y) return 0.5;
+    if (s == 0) return 0.5 * sgn;                               // X: (1/2)[[1, +-1], [+-1, 1]]
+    return x == 0 ? std::complex<double>(0.0, -0.5 * sgn)       // Y: (1/2)[[1, -+i], [+-i, 1]]
+                  : std::complex<double>(0.0, 0.5 * sgn);
+}
+
+std::vector<double> pauli_matrix_packed(int Q)
+{
+    const int D = 1 << Q, D2 = D * D, K = ipow3(Q);
+    std::vector<double> M(static_cast<size_t>(K) * D * D2);
+    std::vector<int> s(Q), bq(Q);
+    for (int k = 0; k < K; ++k) {
+        for (int q = Q - 1, kk = k; q >= 0; --q) { s[q] = kk % 3; kk /= 3; }
+        for (int l = 0; l < D; ++l) {
+            for (int q = 0; q < Q; ++q) bq[q] = (l >> (Q - 1 - q)) & 1;
+            auto Pi = [&](int a, int b) {
+                std::complex<double> v = 1.0;
+                for (int q = 0; q < Q; ++q) v *= qubit_projector(s[q], bq[q], (a >> (Q - 1 - q)) & 1, (b >> (Q - 1 - q)) & 1);
+                return v;
+            };
+            double* row = M.data() + static_cast<size_t>(k * D + l) * D2;
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c)
+                    row[r * D + c] = r == c ? Pi(r, r).real() : (r < c ? 2.0 * Pi(r, c).real() : 2.0 * Pi(c, r).imag());
+        }
+    }
+    return M;
+}
+
+// M in MFMA A-operand fragment order (see the dense contraction in
+// chain_kernel.hpp), as raw bytes of the requested precision.
+std::vector<uint8_t> pauli_fragments(int Q, int prec)
+{
+    const int D = 1 << Q, D2 = D * D, KD = ipow3(Q) * D;
+    const int NT = (KD + 15) / 16;
+    const std::vector<double> M = pauli_matrix_packed(Q);
+    auto m_at = [&](int row, int col) { return (row < KD && col < D2) ? M[static_cast<size_t>(row) * D2 + col] : 0.0; };
+    std::vector<uint8_t> out;
+    if (prec == qst::kPrecF64 || prec == qst::kPrecF32) {
+        const int KS = D2 / 4;
+        const size_t n = static_cast<size_t>(NT) * KS * 64;
+        out.resize(n * (prec == qst::kPrecF64 ? 8 : 4));
+        for (int nt = 0; nt < NT; ++nt)
+            for (int ks = 0; ks < KS; ++ks)
+                for (int l = 0; l < 64; ++l) {
+                    const double v = m_at(16 * nt + l % 16, 4 * ks + l / 16);
+                    const size_t i = (static_cast<size_t>(nt) * KS + ks) * 64 + l;
+                    if (prec == qst::kPrecF64) reinterpret_cast<double*>(out.data())[i] = v;
+                    else reinterpret_cast<float*>(out.data())[i] = static_cast<float>(v);
+                }
+    } else {
+        const int KS = (D2 + 31) / 32;
+        const size_t n = static_cast<size_t>(NT) * KS * 64 * 8;
+        out.resize(n * 2);
+        uint16_t* h = reinterpret_cast<uint16_t*>(out.data());
+        for (int nt = 0; nt < NT; ++nt)
+            for (int ks = 0; ks < KS; ++ks)
+                for (int l = 0; l < 64; ++l)
+                    for (int v = 0; v < 8; ++v) {
+                        const float f = static_cast<float>(m_at(16 * nt + l % 16, 32 * ks + 8 * (l / 16) + v));
+                        uint32_t bits;
+                        std::memcpy(&bits, &f, 4);
+                        if ((bits & 0xFFFFu) != 0) fail(QST_ERR_DEVICE, "Pauli matrix entry not exact in BF16");
+                        h[((static_cast<size_t>(nt) * KS + ks) * 64 + l) * 8 + v] = static_cast<uint16_t>(bits >> 16);
+                    }
+    }
+    return out;
+}
+
 // Launch shape of the chain kernel for one qubit count: team size G (threads
 // per chain) and workgroup size WG.
 struct Shape {
@@ -97,23 +178,43 @@ Shape default_shape(int Q)
     }
 }
 
-template <int Q, int G, int WG>
+template <int Q, int G, int WG, int PATH, int PREC>
 void launch_chains_t(const qst::ChainArgs& a, hipStream_t s)
 {
-    using S = qst::TeamShape<Q, G>;
+    using S = qst::TeamShape<Q, G, PATH>;
     const int64_t teams = WG / G;
     const int64_t blocks = (a.R + teams - 1) / teams;
-    const size_t lds = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q>::kDoubles) * sizeof(double);
+    const size_t lds = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q, PATH>::kDoubles) * sizeof(double);
     static bool attr_done = false;
     if (!attr_done) {
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG>),
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)),
                   "hipFuncSetAttribute");
         attr_done = true;
     }
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many chains for one launch");
-    hipLaunchKernelGGL((qst::k_chains<Q, G, WG>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s, a);
+    hipLaunchKernelGGL((qst::k_chains<Q, G, WG, PATH, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s,
+                       a);
     hip_check(hipGetLastError(), "chain kernel launch");
+}
+
+template <int Q, int PREC>
+void launch_loglik_dense_t(const double* nd, const void* mfrag, const double* rho, int64_t n, double* out,
+                           hipStream_t s)
+{
+    using S = qst::TeamShape<Q, 64, qst::kPathDense>;
+    const int64_t blocks = (n + 15) / 16;
+    const size_t lds = (16 * static_cast<size_t>(S::kLds) + qst::WgTables<Q, qst::kPathDense>::kDoubles) * sizeof(double);
+    static bool attr_done = false;
+    if (!attr_done) {
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_loglik_dense<Q, PREC>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)),
+                  "hipFuncSetAttribute");
+        attr_done = true;
+    }
+    hipLaunchKernelGGL((qst::k_loglik_dense<Q, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(1024), lds, s, nd,
+                       mfrag, rho, n, out);
+    hip_check(hipGetLastError(), "dense loglik kernel launch");
 }
 
 template <int Q, int G, int WG>
@@ -135,10 +236,21 @@ void launch_loglik_t(const double* nd, const double* rho, int64_t n, double* out
     hip_check(hipGetLastError(), "loglik kernel launch");
 }
 
-void launch_chains(int Q, Shape sh, const qst::ChainArgs& a, hipStream_t s)
+void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a, hipStream_t s)
 {
+    using namespace qst;
+    if (path == kPathDense) {
+#define QST_DENSE(q, pr) \
+    if (Q == q && prec == pr) return launch_chains_t<q, 64, 1024, kPathDense, pr>(a, s);
+        QST_DENSE(1, kPrecF64) QST_DENSE(1, kPrecF32) QST_DENSE(1, kPrecBF16x3)
+        QST_DENSE(2, kPrecF64) QST_DENSE(2, kPrecF32) QST_DENSE(2, kPrecBF16x3)
+        QST_DENSE(3, kPrecF64) QST_DENSE(3, kPrecF32) QST_DENSE(3, kPrecBF16x3)
+        QST_DENSE(4, kPrecF64) QST_DENSE(4, kPrecF32) QST_DENSE(4, kPrecBF16x3)
+#undef QST_DENSE
+        fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
+    }
 #define QST_CASE(q, g, wg) \
-    if (Q == q && sh.G == g && sh.WG == wg) return launch_chains_t<q, g, wg>(a, s);
+    if (Q == q && sh.G == g && sh.WG == wg) return launch_chains_t<q, g, wg, kPathKron, kPrecF64>(a, s);
     QST_CASE(1, 8, 64)
     QST_CASE(2, 16, 64)
     QST_CASE(3, 32, 64)
@@ -147,6 +259,20 @@ void launch_chains(int Q, Shape sh, const qst::ChainArgs& a, hipStream_t s)
     QST_CASE(6, 256, 256)
 #undef QST_CASE
     fail(QST_ERR_UNSUPPORTED, "no chain kernel for Q=" + std::to_string(Q) + " G=" + std::to_string(sh.G));
+}
+
+void launch_loglik_dense(int Q, int prec, const double* nd, const void* mfrag, const double* rho, int64_t n,
+                         double* out, hipStream_t s)
+{
+    using namespace qst;
+#define QST_DENSE(q, pr) \
+    if (Q == q && prec == pr) return launch_loglik_dense_t<q, pr>(nd, mfrag, rho, n, out, s);
+    QST_DENSE(1, kPrecF64) QST_DENSE(1, kPrecF32) QST_DENSE(1, kPrecBF16x3)
+    QST_DENSE(2, kPrecF64) QST_DENSE(2, kPrecF32) QST_DENSE(2, kPrecBF16x3)
+    QST_DENSE(3, kPrecF64) QST_DENSE(3, kPrecF32) QST_DENSE(3, kPrecBF16x3)
+    QST_DENSE(4, kPrecF64) QST_DENSE(4, kPrecF32) QST_DENSE(4, kPrecBF16x3)
+#undef QST_DENSE
+    fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
 }
 
 void launch_loglik(int Q, const double* nd, const double* rho, int64_t n, double* out, hipStream_t s)
@@ -180,6 +306,23 @@ struct qst_problem {
     qst_path path = QST_PATH_KRON;
     std::vector<int64_t> counts;
     double* nd = nullptr;  // counts as doubles
+    void* mfrag[3] = {nullptr, nullptr, nullptr};  // dense path: Pauli matrix fragments per precision
+
+    const void* fragments(int prec)
+    {
+        if (!mfrag[prec]) {
+            if (Q > 4) fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
+            const std::vector<uint8_t> f = pauli_fragments(Q, prec);
+            void* d = dev_alloc<uint8_t>(f.size());
+            hipError_t e = hipMemcpy(d, f.data(), f.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(d);
+                fail(QST_ERR_DEVICE, std::string("copy Pauli matrix: ") + hipGetErrorString(e));
+            }
+            mfrag[prec] = d;
+        }
+        return mfrag[prec];
+    }
     // chain state
     int64_t R = 0;
     int64_t step = 0;
@@ -274,9 +417,12 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
         p->KD = p->K * p->D;
         p->device = desc->device;
         p->precision = desc->precision;
-        p->path = desc->path == QST_PATH_AUTO ? QST_PATH_KRON : desc->path;
-        if (p->path == QST_PATH_DENSE || p->precision != QST_FP64)
-            fail(QST_ERR_UNSUPPORTED, "only the FP64 Kronecker path is available in this build");
+        p->path = desc->path == QST_PATH_AUTO ? (desc->precision == QST_FP64 ? QST_PATH_KRON : QST_PATH_DENSE)
+                                              : desc->path;
+        if (p->path == QST_PATH_KRON && p->precision != QST_FP64)
+            fail(QST_ERR_UNSUPPORTED, "the Kronecker path is FP64 only; reduced precision needs QST_PATH_DENSE");
+        if (p->path == QST_PATH_DENSE && Q > 4)
+            fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
         p->counts.assign(desc->counts, desc->counts + p->KD);
         std::vector<double> nd(p->KD);
         for (int i = 0; i < p->KD; ++i) {
@@ -286,6 +432,7 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
         DeviceGuard g(p->device);
         p->nd = dev_alloc<double>(p->KD);
         hip_check(hipMemcpy(p->nd, nd.data(), sizeof(double) * p->KD, hipMemcpyHostToDevice), "copy counts");
+        if (p->path == QST_PATH_DENSE) p->fragments(p->precision);
         *out = p.release();
     });
 }
@@ -299,6 +446,7 @@ void qst_free_problem(qst_problem* p)
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     p->free_state();
     dev_free(p->nd);
+    for (auto& f : p->mfrag) dev_free(f);
     (void)hipSetDevice(prev);
     delete p;
 }
@@ -328,6 +476,7 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
         }
         qst::ChainArgs a{};
         a.nd = p->nd;
+        a.mfrag = p->path == QST_PATH_DENSE ? p->fragments(p->precision) : nullptr;
         a.R = p->R;
         a.x = p->x;
         a.ll = p->ll;
@@ -358,7 +507,8 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
         a.record_every = r.record_every;
         a.record_chains = r.record_chains;
         a.rec = r.record_buf;
-        launch_chains(p->Q, default_shape(p->Q), a, s);
+        launch_chains(p->Q, default_shape(p->Q), p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
+                      static_cast<int>(p->precision), a, s);
         p->step += r.n_steps;
         p->have_run = true;
         p->last_stream = s;
@@ -459,10 +609,17 @@ qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double
         if (n == 0) return;
         if (!rho || !ll_out) fail(QST_ERR_INVALID, "NULL buffer");
         const qst_path pth = path == QST_PATH_AUTO ? p->path : path;
-        if (pth != QST_PATH_KRON || precision != QST_FP64)
-            fail(QST_ERR_UNSUPPORTED, "only the FP64 Kronecker path is available in this build");
+        if (precision != QST_FP64 && precision != QST_FP32 && precision != QST_BF16X3)
+            fail(QST_ERR_INVALID, "unknown precision");
+        if (pth == QST_PATH_KRON && precision != QST_FP64)
+            fail(QST_ERR_UNSUPPORTED, "the Kronecker path is FP64 only");
         DeviceGuard g(p->device);
-        launch_loglik(p->Q, p->nd, rho, n, ll_out, static_cast<hipStream_t>(stream));
+        if (pth == QST_PATH_DENSE) {
+            const void* f = const_cast<qst_problem*>(p)->fragments(precision);
+            launch_loglik_dense(p->Q, precision, p->nd, f, rho, n, ll_out, static_cast<hipStream_t>(stream));
+        } else {
+            launch_loglik(p->Q, p->nd, rho, n, ll_out, static_cast<hipStream_t>(stream));
+        }
     });
 }
 
