@@ -64,6 +64,38 @@ def measured_traffic(kernel_hash, key):
     return ent.get("bytes_per_launch")
 
 
+def dense_gemm_rates(qst, synth, torch, prob, n_states=65536, reps=5):
+    """Throughput of the dense contraction kernel alone (qst_loglik, dense
+    path) on n_states density matrices, per precision: algorithmic GEMM
+    flops 2 KD D^2 per state over the kernel time, against the MFMA peak of
+    the operand type (FP64 78.6, FP32 157.3, BF16 2500 TFLOP/s; BF16x3
+    counts its three products)."""
+    import numpy as np
+    Q, D = prob.n_qubits, 2 ** prob.n_qubits
+    rng = np.random.default_rng(5)
+    base = np.stack([synth.random_density_matrix(D, rng) for _ in range(64)])
+    rhos = np.ascontiguousarray(np.stack([base.real, base.imag], -1)[np.arange(n_states) % 64])
+    dev = torch.from_numpy(rhos).cuda()
+    out = torch.zeros(n_states, dtype=torch.float64, device="cuda")
+    flop = 2.0 * (6 ** Q) * D * D * n_states
+    res = {}
+    for prec, peak, mult in (("fp64", 78.6, 1), ("fp32", 157.3, 1), ("bf16x3", 2500.0, 3)):
+        P = qst.Problem(Q, prob.counts, precision=prec, path="dense")
+        P.loglik(dev, out, path="dense", precision=prec)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            P.loglik(dev, out, path="dense", precision=prec)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        tf = mult * flop / (ms / 1e3) / 1e12
+        res[prec] = {"ms": ms, "tflops": tf, "peak": peak, "frac": tf / peak, "states": n_states}
+        P.close()
+    return res
+
+
 def pilot_beta(qst, P, seed, n_chains=256, n_steps=6000):
     """Algorithm 2's own adaptation (every 100 steps here) run on a pilot set
     of chains; the median final beta starts the measured run."""
@@ -107,6 +139,7 @@ def main():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense-gemm", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -218,6 +251,8 @@ def main():
                      "kernel": f"k_chains<Q={Q}>", "kernel_ms": ms_kernel,
                      "flop_per_chain_step": flop, "kernel_source_hash": khash},
     }
+    if args.config == "c3" and not args.no_dense_gemm:
+        out["dense_gemm"] = dense_gemm_rates(qst, synth, torch, prob)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
