@@ -148,13 +148,30 @@ typedef struct {
 qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out);
 
 /* Step 5 / Algorithm 2 on every problem of the batch in ONE persistent
- * kernel launch per call (a batch of several handles is the uneven-batch
- * form: each problem's results are identical to running it alone).  All
- * handles must live on the same device.  Work is queued on runs[0].stream;
- * the call returns without waiting unless stats is non-NULL, in which case
- * it waits and fills stats[i] for every problem. */
+ * kernel launch per call.  A batch of several handles is the uneven-batch
+ * form: problems of 1..6 qubits with any chain counts are cut into workgroup
+ * tiles, ordered largest-cost first, and taken from a device work counter by
+ * resident workgroups; each problem's results are bit-identical to running
+ * it alone with the same team size (qst_set_launch_shape), and equal up to
+ * summation order otherwise.  Batches need the FP64 Kronecker path (QST_ERR_UNSUPPORTED
+ * otherwise), distinct handles on one device, and use runs[0].stream.  A
+ * single-problem call returns without waiting unless stats is non-NULL; a
+ * batch call waits for completion.  stats (host, [n_problems]) is filled
+ * when non-NULL. */
 qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems,
                           const qst_run_desc* runs, qst_run_stats* stats);
+
+/* Launch shape of the single-problem chain kernel for one qubit count:
+ * `team` threads per chain, `workgroup` threads per workgroup.  Only shapes
+ * with a compiled kernel are accepted (qst_list_launch_shapes); the
+ * autotuner (paper_2501_17334_amd/tune.py) times them and installs the
+ * fastest.  Process-wide setting, not thread-safe. */
+qst_status qst_set_launch_shape(int32_t n_qubits, int32_t team, int32_t workgroup);
+qst_status qst_get_launch_shape(int32_t n_qubits, int32_t* team, int32_t* workgroup);
+/* The compiled shapes for n_qubits: up to `capacity` (team, workgroup) pairs
+ * into the host arrays; *count receives how many exist. */
+qst_status qst_list_launch_shapes(int32_t n_qubits, int32_t* teams, int32_t* workgroups, int32_t capacity,
+                                  int32_t* count);
 
 /* Step 6 / Eq. (BME2): pooled mean over every stored sample of every chain
  * (host, D*D*2 interleaved complex).  Optional host outputs (NULL to skip):

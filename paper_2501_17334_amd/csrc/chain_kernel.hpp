@@ -788,11 +788,20 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
     }
 }
 
-#ifndef QST_CHAIN_MIN_WAVES
-#define QST_CHAIN_MIN_WAVES 4
-#endif
+// Waves per SIMD the register allocation aims at: the per-lane state
+// (NYL + 4 NPL doubles) plus about 64 registers of temporaries, within the
+// 512-register file of a SIMD lane, at most 4.
+template <int Q, int G>
+constexpr int chain_min_waves()
+{
+    using S = TeamShape<Q, G>;
+    const int regs = 2 * (S::NYL + 4 * S::NPL) + 64;
+    const int w = 512 / regs;
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
 template <int Q, int G, int WG, int PATH = kPathKron, int PREC = kPrecF64>
-__global__ __launch_bounds__(WG, (WG <= 64 ? QST_CHAIN_MIN_WAVES : 1)) void k_chains(ChainArgs A)
+__global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainArgs A)
 {
     extern __shared__ double lds[];
     wg_tables_init<Q, PATH>(lds, threadIdx.x, WG);

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -15,6 +16,7 @@
 
 #include "../../include/qst.h"
 #include "acf_kernel.hpp"
+#include "batch_kernel.hpp"
 #include "chain_kernel.hpp"
 #include "pool_kernel.hpp"
 
@@ -166,16 +168,28 @@ struct Shape {
     int G, WG;
 };
 
-Shape default_shape(int Q)
+// Shapes with a compiled single-problem chain kernel (Kronecker path).
+constexpr Shape kShapes[7][5] = {
+    {},
+    {{8, 64}, {16, 64}, {64, 64}},
+    {{16, 64}, {32, 64}, {64, 64}},
+    {{32, 64}, {64, 64}},
+    {{64, 64}, {64, 256}},
+    {{64, 64}, {128, 128}, {256, 256}, {512, 512}},
+    {{256, 256}, {512, 512}},
+};
+
+// Current choice per qubit count (set by qst_set_launch_shape, e.g. from the
+// autotuner's table).
+Shape g_shape[7] = {{0, 0}, {8, 64}, {16, 64}, {32, 64}, {64, 256}, {256, 256}, {512, 512}};
+
+Shape current_shape(int Q) { return g_shape[Q]; }
+
+bool shape_compiled(int Q, Shape sh)
 {
-    switch (Q) {
-        case 1: return {8, 64};
-        case 2: return {16, 64};
-        case 3: return {32, 64};
-        case 4: return {64, 64};
-        case 5: return {64, 64};
-        default: return {256, 256};
-    }
+    for (const Shape& c : kShapes[Q])
+        if (c.G == sh.G && c.WG == sh.WG && c.G > 0) return true;
+    return false;
 }
 
 template <int Q, int G, int WG, int PATH, int PREC>
@@ -251,12 +265,12 @@ void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a,
     }
 #define QST_CASE(q, g, wg) \
     if (Q == q && sh.G == g && sh.WG == wg) return launch_chains_t<q, g, wg, kPathKron, kPrecF64>(a, s);
-    QST_CASE(1, 8, 64)
-    QST_CASE(2, 16, 64)
-    QST_CASE(3, 32, 64)
-    QST_CASE(4, 64, 64)
-    QST_CASE(5, 64, 64)
-    QST_CASE(6, 256, 256)
+    QST_CASE(1, 8, 64) QST_CASE(1, 16, 64) QST_CASE(1, 64, 64)
+    QST_CASE(2, 16, 64) QST_CASE(2, 32, 64) QST_CASE(2, 64, 64)
+    QST_CASE(3, 32, 64) QST_CASE(3, 64, 64)
+    QST_CASE(4, 64, 64) QST_CASE(4, 64, 256)
+    QST_CASE(5, 64, 64) QST_CASE(5, 128, 128) QST_CASE(5, 256, 256) QST_CASE(5, 512, 512)
+    QST_CASE(6, 256, 256) QST_CASE(6, 512, 512)
 #undef QST_CASE
     fail(QST_ERR_UNSUPPORTED, "no chain kernel for Q=" + std::to_string(Q) + " G=" + std::to_string(sh.G));
 }
@@ -451,6 +465,180 @@ void qst_free_problem(qst_problem* p)
     delete p;
 }
 
+}  // extern "C"
+
+namespace {
+
+void prepare_state(qst_problem* p, const qst_run_desc& r)
+{
+    if (!r.resume) {
+        if (p->R != r.n_chains) {
+            if (p->last_stream) hip_check(hipStreamSynchronize(p->last_stream), "sync before realloc");
+            p->alloc_state(r.n_chains);
+        }
+        p->step = 0;
+    }
+}
+
+qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
+{
+    qst::ChainArgs a{};
+    a.nd = p->nd;
+    a.mfrag = p->path == QST_PATH_DENSE ? p->fragments(p->precision) : nullptr;
+    a.R = p->R;
+    a.x = p->x;
+    a.ll = p->ll;
+    a.beta = p->beta;
+    a.acc_win = p->accw;
+    a.rho_cur = p->rho;
+    a.s1 = p->s1;
+    a.s2 = p->s2;
+    a.n_stored = p->nst;
+    a.n_acc = p->nacc;
+    a.n_near = p->nnear;
+    a.step_begin = p->step;
+    a.n_steps = r.n_steps;
+    a.burn_in = r.burn_in;
+    a.adapt_until = r.adapt_until;
+    a.thin = r.thin;
+    a.adapt_every = r.adapt_every;
+    a.init = r.resume ? 0 : 1;
+    a.beta0 = r.beta0;
+    a.adapt_lo = r.adapt_lo;
+    a.adapt_hi = r.adapt_hi;
+    a.adapt_factor = r.adapt_factor;
+    a.seed = r.seed;
+    a.trace_chains = r.trace_chains;
+    a.tr_ll = r.trace_llprop;
+    a.tr_lu = r.trace_logu;
+    a.tr_acc = r.trace_accept;
+    a.record_every = r.record_every;
+    a.record_chains = r.record_chains;
+    a.rec = r.record_buf;
+    return a;
+}
+
+qst_run_stats collect_stats(const qst_problem* p, const qst_run_desc& r)
+{
+    std::vector<int64_t> nacc(p->R), nnear(p->R);
+    std::vector<double> ll(p->R), beta(p->R);
+    hip_check(hipMemcpy(nacc.data(), p->nacc, sizeof(int64_t) * p->R, hipMemcpyDeviceToHost), "stats");
+    hip_check(hipMemcpy(nnear.data(), p->nnear, sizeof(int64_t) * p->R, hipMemcpyDeviceToHost), "stats");
+    hip_check(hipMemcpy(ll.data(), p->ll, sizeof(double) * p->R, hipMemcpyDeviceToHost), "stats");
+    hip_check(hipMemcpy(beta.data(), p->beta, sizeof(double) * p->R, hipMemcpyDeviceToHost), "stats");
+    qst_run_stats st{};
+    st.proposed = p->R * r.n_steps;
+    st.beta_min = INFINITY;
+    st.beta_max = -INFINITY;
+    for (int64_t c = 0; c < p->R; ++c) {
+        st.accepted += nacc[c];
+        st.near_threshold += nnear[c];
+        st.nonfinite_chains += std::isfinite(ll[c]) ? 0 : 1;
+        st.beta_min = std::fmin(st.beta_min, beta[c]);
+        st.beta_max = std::fmax(st.beta_max, beta[c]);
+    }
+    st.stage1_passed = st.proposed;
+    return st;
+}
+
+int batch_team(int Q)
+{
+    switch (Q) {
+        case 1: return qst::BatchTeam<1>::G;
+        case 2: return qst::BatchTeam<2>::G;
+        case 3: return qst::BatchTeam<3>::G;
+        case 4: return qst::BatchTeam<4>::G;
+        case 5: return qst::BatchTeam<5>::G;
+        default: return qst::BatchTeam<6>::G;
+    }
+}
+
+size_t batch_lds_bytes(int Q)
+{
+    switch (Q) {
+        case 1: return qst::batch_lds_doubles<1>() * sizeof(double);
+        case 2: return qst::batch_lds_doubles<2>() * sizeof(double);
+        case 3: return qst::batch_lds_doubles<3>() * sizeof(double);
+        case 4: return qst::batch_lds_doubles<4>() * sizeof(double);
+        case 5: return qst::batch_lds_doubles<5>() * sizeof(double);
+        default: return qst::batch_lds_doubles<6>() * sizeof(double);
+    }
+}
+
+// Relative cost of one chain-step per qubit count (largest-first ordering of
+// batch tiles; only the order matters).
+double chain_step_cost(int Q)
+{
+    static const double c[7] = {0.0, 1.0, 1.5, 3.0, 10.0, 60.0, 400.0};
+    return c[Q];
+}
+
+void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* runs, hipStream_t s)
+{
+    std::vector<qst::ChainArgs> args(n);
+    std::vector<qst::BatchItem> items;
+    std::vector<double> cost;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+        qst_problem* p = problems[i];
+        if (p->path != QST_PATH_KRON) fail(QST_ERR_UNSUPPORTED, "batched launches use the FP64 Kronecker path");
+        args[i] = make_args(p, runs[i]);
+        const int per = qst::kBatchWG / batch_team(p->Q);
+        for (int64_t c0 = 0; c0 < p->R; c0 += per) {
+            items.push_back({i, p->Q, c0});
+            cost.push_back(chain_step_cost(p->Q) * static_cast<double>(std::min<int64_t>(per, p->R - c0)) *
+                           static_cast<double>(std::max<int64_t>(runs[i].n_steps, 1)));
+        }
+        lds = std::max(lds, batch_lds_bytes(p->Q));
+    }
+    std::vector<size_t> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<qst::BatchItem> sorted(items.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+    if (sorted.size() > 0x7fffffff) fail(QST_ERR_INVALID, "batch too large");
+
+    qst::ChainArgs* dargs = dev_alloc<qst::ChainArgs>(args.size());
+    qst::BatchItem* ditems = nullptr;
+    int32_t* counter = nullptr;
+    try {
+        ditems = dev_alloc<qst::BatchItem>(sorted.size());
+        counter = dev_alloc<int32_t>(1);
+        hip_check(hipMemcpy(dargs, args.data(), sizeof(qst::ChainArgs) * args.size(), hipMemcpyHostToDevice),
+                  "copy batch problems");
+        hip_check(hipMemcpy(ditems, sorted.data(), sizeof(qst::BatchItem) * sorted.size(), hipMemcpyHostToDevice),
+                  "copy batch tiles");
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_chains_batch),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)),
+                  "hipFuncSetAttribute");
+        int dev = 0, n_cu = 0, per_cu = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+        hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qst::k_chains_batch, qst::kBatchWG, lds),
+                  "occupancy");
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(sorted.size()),
+                                                                     static_cast<int64_t>(n_cu) * std::max(per_cu, 1)));
+        hipLaunchKernelGGL(qst::k_zero_counter, dim3(1), dim3(1), 0, s, counter);
+        hip_check(hipGetLastError(), "counter reset");
+        qst::BatchArgs b{dargs, ditems, static_cast<int32_t>(sorted.size()), counter};
+        hipLaunchKernelGGL(qst::k_chains_batch, dim3(static_cast<unsigned>(grid)), dim3(qst::kBatchWG), lds, s, b);
+        hip_check(hipGetLastError(), "batch kernel launch");
+        hip_check(hipStreamSynchronize(s), "batch synchronize");
+    } catch (...) {
+        dev_free(dargs);
+        dev_free(ditems);
+        dev_free(counter);
+        throw;
+    }
+    dev_free(dargs);
+    dev_free(ditems);
+    dev_free(counter);
+}
+
+}  // namespace
+
+extern "C" {
+
 qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, const qst_run_desc* runs,
                           qst_run_stats* stats)
 {
@@ -460,80 +648,69 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
         for (int i = 0; i < n_problems; ++i) {
             if (!problems[i]) fail(QST_ERR_INVALID, "NULL problem handle");
             if (problems[i]->device != dev) fail(QST_ERR_INVALID, "batch spans several devices");
+            for (int j = 0; j < i; ++j)
+                if (problems[j] == problems[i]) fail(QST_ERR_INVALID, "a handle appears twice in the batch");
             validate_run(problems[i], runs[i]);
         }
-        if (n_problems > 1) fail(QST_ERR_UNSUPPORTED, "batched launch is not available in this build");
         DeviceGuard g(dev);
-        qst_problem* p = problems[0];
-        const qst_run_desc& r = runs[0];
-        hipStream_t s = static_cast<hipStream_t>(r.stream);
-        if (!r.resume) {
-            if (p->R != r.n_chains) {
-                if (p->last_stream) hip_check(hipStreamSynchronize(p->last_stream), "sync before realloc");
-                p->alloc_state(r.n_chains);
-            }
-            p->step = 0;
+        hipStream_t s = static_cast<hipStream_t>(runs[0].stream);
+        for (int i = 0; i < n_problems; ++i) prepare_state(problems[i], runs[i]);
+        if (n_problems == 1) {
+            qst_problem* p = problems[0];
+            const qst::ChainArgs a = make_args(p, runs[0]);
+            launch_chains(p->Q, current_shape(p->Q), p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
+                          static_cast<int>(p->precision), a, s);
+        } else {
+            launch_batch(problems, n_problems, runs, s);
         }
-        qst::ChainArgs a{};
-        a.nd = p->nd;
-        a.mfrag = p->path == QST_PATH_DENSE ? p->fragments(p->precision) : nullptr;
-        a.R = p->R;
-        a.x = p->x;
-        a.ll = p->ll;
-        a.beta = p->beta;
-        a.acc_win = p->accw;
-        a.rho_cur = p->rho;
-        a.s1 = p->s1;
-        a.s2 = p->s2;
-        a.n_stored = p->nst;
-        a.n_acc = p->nacc;
-        a.n_near = p->nnear;
-        a.step_begin = p->step;
-        a.n_steps = r.n_steps;
-        a.burn_in = r.burn_in;
-        a.adapt_until = r.adapt_until;
-        a.thin = r.thin;
-        a.adapt_every = r.adapt_every;
-        a.init = r.resume ? 0 : 1;
-        a.beta0 = r.beta0;
-        a.adapt_lo = r.adapt_lo;
-        a.adapt_hi = r.adapt_hi;
-        a.adapt_factor = r.adapt_factor;
-        a.seed = r.seed;
-        a.trace_chains = r.trace_chains;
-        a.tr_ll = r.trace_llprop;
-        a.tr_lu = r.trace_logu;
-        a.tr_acc = r.trace_accept;
-        a.record_every = r.record_every;
-        a.record_chains = r.record_chains;
-        a.rec = r.record_buf;
-        launch_chains(p->Q, default_shape(p->Q), p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
-                      static_cast<int>(p->precision), a, s);
-        p->step += r.n_steps;
-        p->have_run = true;
-        p->last_stream = s;
+        for (int i = 0; i < n_problems; ++i) {
+            problems[i]->step += runs[i].n_steps;
+            problems[i]->have_run = true;
+            problems[i]->last_stream = s;
+        }
         if (stats) {
             hip_check(hipStreamSynchronize(s), "run synchronize");
-            std::vector<int64_t> nacc(p->R), nnear(p->R);
-            std::vector<double> ll(p->R), beta(p->R);
-            hip_check(hipMemcpy(nacc.data(), p->nacc, sizeof(int64_t) * p->R, hipMemcpyDeviceToHost), "stats");
-            hip_check(hipMemcpy(nnear.data(), p->nnear, sizeof(int64_t) * p->R, hipMemcpyDeviceToHost), "stats");
-            hip_check(hipMemcpy(ll.data(), p->ll, sizeof(double) * p->R, hipMemcpyDeviceToHost), "stats");
-            hip_check(hipMemcpy(beta.data(), p->beta, sizeof(double) * p->R, hipMemcpyDeviceToHost), "stats");
-            qst_run_stats st{};
-            st.proposed = p->R * r.n_steps;
-            st.beta_min = INFINITY;
-            st.beta_max = -INFINITY;
-            for (int64_t c = 0; c < p->R; ++c) {
-                st.accepted += nacc[c];
-                st.near_threshold += nnear[c];
-                st.nonfinite_chains += std::isfinite(ll[c]) ? 0 : 1;
-                st.beta_min = std::fmin(st.beta_min, beta[c]);
-                st.beta_max = std::fmax(st.beta_max, beta[c]);
-            }
-            st.stage1_passed = st.proposed;
-            stats[0] = st;
+            for (int i = 0; i < n_problems; ++i) stats[i] = collect_stats(problems[i], runs[i]);
         }
+    });
+}
+
+qst_status qst_set_launch_shape(int32_t n_qubits, int32_t team, int32_t workgroup)
+{
+    return guarded([&] {
+        if (n_qubits < 1 || n_qubits > 6) fail(QST_ERR_INVALID, "n_qubits must be in 1..6");
+        const Shape sh{team, workgroup};
+        if (!shape_compiled(n_qubits, sh)) fail(QST_ERR_UNSUPPORTED, "no chain kernel compiled for this shape");
+        g_shape[n_qubits] = sh;
+    });
+}
+
+qst_status qst_get_launch_shape(int32_t n_qubits, int32_t* team, int32_t* workgroup)
+{
+    return guarded([&] {
+        if (n_qubits < 1 || n_qubits > 6) fail(QST_ERR_INVALID, "n_qubits must be in 1..6");
+        if (!team || !workgroup) fail(QST_ERR_INVALID, "NULL output");
+        *team = g_shape[n_qubits].G;
+        *workgroup = g_shape[n_qubits].WG;
+    });
+}
+
+qst_status qst_list_launch_shapes(int32_t n_qubits, int32_t* teams, int32_t* workgroups, int32_t capacity,
+                                  int32_t* count)
+{
+    return guarded([&] {
+        if (n_qubits < 1 || n_qubits > 6) fail(QST_ERR_INVALID, "n_qubits must be in 1..6");
+        if (!count) fail(QST_ERR_INVALID, "NULL count");
+        int32_t n = 0;
+        for (const Shape& c : kShapes[n_qubits]) {
+            if (c.G <= 0) continue;
+            if (teams && workgroups && n < capacity) {
+                teams[n] = c.G;
+                workgroups[n] = c.WG;
+            }
+            ++n;
+        }
+        *count = n;
     });
 }
 

@@ -67,6 +67,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_2501_17334_amd/build.py)")
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes libqst.so bind to that one runtime, so torch's streams and
+        # allocations are the library's too
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.qst_init_problem.argtypes = [C.POINTER(_ProblemDesc), C.POINTER(vp)]
@@ -77,15 +81,33 @@ def lib():
                                       C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.qst_loglik.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_int, vp]
         L.qst_acf.argtypes = [vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
+        L.qst_set_launch_shape.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        L.qst_get_launch_shape.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.qst_list_launch_shapes.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
+                                             C.POINTER(C.c_int32)]
         L.qst_free_problem.argtypes = [vp]
         L.qst_free_problem.restype = None
         L.qst_last_error.restype = C.c_char_p
         L.qst_version.restype = C.c_char_p
         for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state",
-                  "qst_loglik", "qst_acf"):
+                  "qst_loglik", "qst_acf", "qst_set_launch_shape", "qst_get_launch_shape",
+                  "qst_list_launch_shapes"):
             getattr(L, f).restype = C.c_int
         _lib = L
+        _install_tuned_shapes()
     return _lib
+
+
+def _install_tuned_shapes():
+    """Apply the autotuner's saved launch shapes (tune_gfx950.json), if any."""
+    import json
+    path = os.path.join(_HERE, "tune_gfx950.json")
+    if not os.path.exists(path):
+        return
+    with open(path) as f:
+        table = json.load(f)
+    for q, ent in table.items():
+        _lib.qst_set_launch_shape(int(q), int(ent["team"]), int(ent["workgroup"]))
 
 
 def _check(status):
@@ -209,6 +231,39 @@ class Problem:
         _check(lib().qst_loglik(self._h, C.c_void_p(rho_dev.data_ptr()), n, C.c_void_p(out_dev.data_ptr()),
                                 _PATH[path], _PREC[precision],
                                 stream if stream is not None else current_stream()))
+
+
+def set_launch_shape(n_qubits, team, workgroup):
+    _check(lib().qst_set_launch_shape(n_qubits, team, workgroup))
+
+
+def get_launch_shape(n_qubits):
+    t, w = C.c_int32(), C.c_int32()
+    _check(lib().qst_get_launch_shape(n_qubits, C.byref(t), C.byref(w)))
+    return t.value, w.value
+
+
+def list_launch_shapes(n_qubits):
+    n = C.c_int32()
+    _check(lib().qst_list_launch_shapes(n_qubits, None, None, 0, C.byref(n)))
+    T = (C.c_int32 * n.value)()
+    W = (C.c_int32 * n.value)()
+    _check(lib().qst_list_launch_shapes(n_qubits, T, W, n.value, C.byref(n)))
+    return list(zip(T, W))
+
+
+def run_batch(problems, configs, stats=True, stream=None):
+    """qst_run_chains on several problems in one launch (the uneven batch)."""
+    n = len(problems)
+    rds = (_RunDesc * n)(*[p._run_desc(c, None, None, stream) for p, c in zip(problems, configs)])
+    hs = (C.c_void_p * n)(*[p._h for p in problems])
+    st = (_RunStats * n)()
+    _check(lib().qst_run_chains(hs, n, rds, st if stats else None))
+    for p, c in zip(problems, configs):
+        p.n_chains = c.n_chains
+    if stats:
+        return [{f: getattr(s, f) for f, _ in _RunStats._fields_} for s in st]
+    return None
 
 
 def acf(records_dev, l_max=200, stream=None):

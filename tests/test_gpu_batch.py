@@ -1,0 +1,96 @@
+"""Uneven batches in one persistent launch, and the launch-shape tuner.
+
+A batch of problems of 1..6 qubits must give each problem exactly (bit for
+bit) what running it alone gives with the same team size, because every
+random number is keyed by (seed, problem-local chain id, step).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2501_17334_amd import qst, synth
+
+pytestmark = pytest.mark.gpu
+
+BATCH_TEAM = {1: 8, 2: 16, 3: 32, 4: 64, 5: 512, 6: 512}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problems():
+    by_q = {}
+    for p in synth.mixed_batch(256):
+        by_q.setdefault(p.n_qubits, p)
+    return [by_q[q] for q in range(1, 7)]
+
+
+def test_batch_equals_solo():
+    probs = _problems()
+    chains = {1: 70, 2: 45, 3: 21, 4: 9, 5: 3, 6: 2}
+    steps = {1: 300, 2: 200, 3: 100, 4: 40, 5: 6, 6: 2}
+    cfgs = [qst.RunConfig(n_chains=chains[p.n_qubits], n_steps=steps[p.n_qubits], seed=p.seed, beta0=0.05,
+                          adapt_every=20, burn_in=1) for p in probs]
+    batch = [qst.Problem(p.n_qubits, p.counts) for p in probs]
+    print("[batch] run", flush=True)
+    st_b = qst.run_batch(batch, cfgs)
+    saved = {q: qst.get_launch_shape(q) for q in range(1, 7)}
+    try:
+        for q in range(1, 7):
+            qst.set_launch_shape(q, BATCH_TEAM[q], max(64, BATCH_TEAM[q]))
+        for p, cfg, b, sb in zip(probs, cfgs, batch, st_b):
+            print(f"[batch] solo Q={p.n_qubits}", flush=True)
+            solo = qst.Problem(p.n_qubits, p.counts)
+            st = solo.run(cfg)
+            xs, lls, bs, ns = solo.state()
+            xb, llb, bb, nb = b.state()
+            assert np.array_equal(xs, xb) and np.array_equal(lls, llb)
+            assert np.array_equal(bs, bb) and np.array_equal(ns, nb)
+            assert np.array_equal(solo.pool()["mean"], b.pool()["mean"])
+            assert st["accepted"] == sb["accepted"]
+    finally:
+        for q, sh in saved.items():
+            qst.set_launch_shape(q, *sh)
+
+
+def test_batch_resume_and_stats():
+    probs = _problems()[:4]
+    cfgs = [qst.RunConfig(n_chains=33, n_steps=50, seed=p.seed, beta0=0.05, adapt_every=25) for p in probs]
+    batch = [qst.Problem(p.n_qubits, p.counts) for p in probs]
+    st = qst.run_batch(batch, cfgs)
+    assert [s["proposed"] for s in st] == [33 * 50] * 4
+    cfgs2 = [qst.RunConfig(n_chains=33, n_steps=30, seed=p.seed, beta0=0.05, adapt_every=25, resume=True)
+             for p in probs]
+    qst.run_batch(batch, cfgs2)
+    for p, b in zip(probs, batch):
+        one = qst.Problem(p.n_qubits, p.counts)
+        qst.run_batch([one, qst.Problem(1, synth.make_problem("c1").counts)],
+                      [qst.RunConfig(n_chains=33, n_steps=80, seed=p.seed, beta0=0.05, adapt_every=25),
+                       qst.RunConfig(n_chains=5, n_steps=3, seed=1, beta0=0.1)])
+        assert np.array_equal(one.state()[0], b.state()[0])
+
+
+def test_batch_rejects_dense_and_duplicates():
+    p = synth.make_problem("c3")
+    a = qst.Problem(4, p.counts, precision="bf16x3", path="dense")
+    b = qst.Problem(4, p.counts)
+    cfg = qst.RunConfig(n_chains=4, n_steps=2, seed=1, beta0=0.1)
+    with pytest.raises(qst.QstError) as e:
+        qst.run_batch([a, b], [cfg, cfg])
+    assert e.value.status == qst.QST_ERR_UNSUPPORTED
+    with pytest.raises(qst.QstError) as e:
+        qst.run_batch([b, b], [cfg, cfg])
+    assert e.value.status == qst.QST_ERR_INVALID
+
+
+def test_launch_shapes_roundtrip():
+    for q in range(1, 7):
+        shapes = qst.list_launch_shapes(q)
+        assert len(shapes) >= 1
+        cur = qst.get_launch_shape(q)
+        assert cur in shapes
+    with pytest.raises(qst.QstError):
+        qst.set_launch_shape(4, 3, 64)
