@@ -93,6 +93,8 @@ typedef struct {
  * All pointers are DEVICE pointers owned by the caller and must stay valid
  * while a run uses them.  W1 is [h1][d] and W2 [h2][h1], row-major, BF16
  * (uint16 bit patterns); biases and w3 are FP32. */
+typedef struct qst_mlp qst_mlp;            /* opaque; an MLP and its training state on one device */
+
 typedef struct {
     int32_t h1, h2;
     const uint16_t* W1;
@@ -102,6 +104,7 @@ typedef struct {
     const float* w3;
     float b3;
     float out_scale, out_shift;
+    qst_mlp* model;          /* the MLP these pointers belong to (filled by qst_mlp_surrogate) */
 } qst_surrogate;
 
 typedef struct {
@@ -201,6 +204,34 @@ qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double
  * Waits for completion. */
 qst_status qst_acf(const double* records, int64_t n_chains, int64_t n_samples, int32_t n_qubits,
                    int32_t l_max, double* out, void* stream);
+
+/* ---------------------------------------------------------------------
+ * MLP surrogate of log L for delayed acceptance (spec form 4):
+ * h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2), s = w3 . h2 + b3 (exact erf
+ * GELU, Hendrycks & Gimpel 2016), trained by mean squared error and Adam
+ * (Kingma & Ba 2015, beta 0.9/0.999, eps 1e-8) with the library's own
+ * forward and backward kernels: BF16 operands on MFMA, FP32 accumulation,
+ * FP32 master weights.  Parameters travel as one flat FP32 array
+ * [W1 (h1 x d, row-major) | b1 | W2 (h2 x h1) | b2 | w3 | b3].
+ * Batches x are DEVICE arrays of n rows of d BF16 values (uint16 bits),
+ * targets y DEVICE FP32; n a multiple of 32.
+ * --------------------------------------------------------------------- */
+qst_status qst_mlp_create(int32_t d_in, int32_t h1, int32_t h2, int32_t device, qst_mlp** out);
+void qst_mlp_free(qst_mlp* h);
+int64_t qst_mlp_num_params(const qst_mlp* h);
+/* host params [n_par]; the prediction is out_scale * s + out_shift; resets Adam */
+qst_status qst_mlp_set_params(qst_mlp* h, const float* params, int64_t n, float out_scale, float out_shift);
+qst_status qst_mlp_get_params(const qst_mlp* h, float* params, int64_t n);
+/* gradients of mean (s - y)^2 (host [n_par], nullable) and the loss (host, nullable); waits */
+qst_status qst_mlp_gradients(qst_mlp* h, const uint16_t* x, const float* y, int64_t n, float* grad_host,
+                             float* loss_host, void* stream);
+/* one Adam step on a minibatch; loss_host (nullable) waits for and returns the pre-step loss */
+qst_status qst_mlp_train_step(qst_mlp* h, const uint16_t* x, const float* y, int64_t n, float lr, float* loss_host,
+                              void* stream);
+/* out (DEVICE FP32 [n]) = out_scale * s(x) + out_shift */
+qst_status qst_mlp_predict(qst_mlp* h, const uint16_t* x, int64_t n, float* out, void* stream);
+/* the frozen surrogate for qst_run_desc.surrogate (pointers into h; valid while h lives) */
+qst_status qst_mlp_surrogate(const qst_mlp* h, qst_surrogate* out);
 
 void qst_free_problem(qst_problem* p);
 const char* qst_last_error(void);

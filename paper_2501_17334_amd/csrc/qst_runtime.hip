@@ -18,6 +18,7 @@
 #include "acf_kernel.hpp"
 #include "batch_kernel.hpp"
 #include "chain_kernel.hpp"
+#include "mlp_kernels.hpp"
 #include "pool_kernel.hpp"
 
 namespace {
@@ -830,6 +831,317 @@ qst_status qst_acf(const double* records, int64_t n_chains, int64_t n_samples, i
         }
         dev_free(part);
         dev_free(outd);
+    });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// MLP surrogate (delayed acceptance): parameters, workspaces, training step
+// ===========================================================================
+struct qst_mlp {
+    int d = 0, h1 = 0, h2 = 0, device = 0;
+    int64_t n_par = 0;
+    int64_t t = 0;                 // Adam steps taken
+    float out_scale = 1.0f, out_shift = 0.0f;
+    float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+    uint16_t *W1b = nullptr, *W2b = nullptr, *W2T = nullptr;
+    // workspace for batches up to cap rows
+    int64_t cap = 0;
+    float *Z1 = nullptr, *Z2 = nullptr, *s = nullptr, *ds = nullptr, *sq = nullptr, *part = nullptr, *loss = nullptr;
+    uint16_t *H1 = nullptr, *H2 = nullptr, *dZ2 = nullptr, *dZ1 = nullptr, *dZ2T = nullptr, *H1T = nullptr,
+             *dZ1T = nullptr, *XT = nullptr;
+
+    int64_t off_W1() const { return 0; }
+    int64_t off_b1() const { return static_cast<int64_t>(h1) * d; }
+    int64_t off_W2() const { return off_b1() + h1; }
+    int64_t off_b2() const { return off_W2() + static_cast<int64_t>(h2) * h1; }
+    int64_t off_w3() const { return off_b2() + h2; }
+    int64_t off_b3() const { return off_w3() + h2; }
+
+    void free_work()
+    {
+        dev_free(Z1); dev_free(Z2); dev_free(s); dev_free(ds); dev_free(sq); dev_free(part); dev_free(loss);
+        dev_free(H1); dev_free(H2); dev_free(dZ2); dev_free(dZ1); dev_free(dZ2T); dev_free(H1T); dev_free(dZ1T);
+        dev_free(XT);
+        cap = 0;
+    }
+    void ensure(int64_t n)
+    {
+        if (n <= cap) return;
+        free_work();
+        const int64_t c = (n + 63) / 64 * 64;
+        const int64_t hmax = std::max(h1, h2);
+        Z1 = dev_alloc<float>(c * h1);
+        Z2 = dev_alloc<float>(c * h2);
+        s = dev_alloc<float>(c);
+        ds = dev_alloc<float>(c);
+        sq = dev_alloc<float>(c);
+        part = dev_alloc<float>(((c + qst::kColChunk - 1) / qst::kColChunk) * std::max<int64_t>(hmax, 1));
+        loss = dev_alloc<float>(1);
+        H1 = dev_alloc<uint16_t>(c * h1);
+        H2 = dev_alloc<uint16_t>(c * h2);
+        dZ2 = dev_alloc<uint16_t>(c * h2);
+        dZ1 = dev_alloc<uint16_t>(c * h1);
+        dZ2T = dev_alloc<uint16_t>(c * h2);
+        H1T = dev_alloc<uint16_t>(c * h1);
+        dZ1T = dev_alloc<uint16_t>(c * h1);
+        XT = dev_alloc<uint16_t>(c * d);
+        cap = c;
+    }
+    void free_all()
+    {
+        free_work();
+        dev_free(theta); dev_free(grad); dev_free(m); dev_free(v); dev_free(W1b); dev_free(W2b); dev_free(W2T);
+    }
+};
+
+namespace {
+
+inline unsigned blocks_for(int64_t n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
+
+void mlp_refresh_bf16(qst_mlp* h, hipStream_t s)
+{
+    const int64_t n1 = static_cast<int64_t>(h->h1) * h->d, n2 = static_cast<int64_t>(h->h2) * h->h1;
+    hipLaunchKernelGGL(qst::k_f32_to_bf16, dim3(blocks_for(n1, 256)), dim3(256), 0, s, h->theta + h->off_W1(), n1, h->W1b);
+    hipLaunchKernelGGL(qst::k_f32_to_bf16, dim3(blocks_for(n2, 256)), dim3(256), 0, s, h->theta + h->off_W2(), n2, h->W2b);
+    hip_check(hipGetLastError(), "weight conversion");
+}
+
+template <int EPI>
+void gemm(int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb, float* C, int ldc,
+          const float* bias, const float* Zin, float* Zout, uint16_t* H, int ldh, hipStream_t s)
+{
+    if (K % qst::kMlpBK != 0) fail(QST_ERR_INVALID, "product length must be a multiple of 32");
+    const dim3 grid(blocks_for(N, qst::kMlpTile), blocks_for(M, qst::kMlpTile));
+    hipLaunchKernelGGL((qst::k_gemm_nt_bf16<EPI>), grid, dim3(256), 0, s, M, N, A, lda, B, ldb, K, C, ldc, bias, Zin,
+                       Zout, H, ldh);
+    hip_check(hipGetLastError(), "MLP product launch");
+}
+
+void colsum(const uint16_t* in, const float* w, int64_t rows, int cols, float* part, float* out, hipStream_t s)
+{
+    const int nchunks = static_cast<int>((rows + qst::kColChunk - 1) / qst::kColChunk);
+    hipLaunchKernelGGL(qst::k_colsum_partial, dim3(blocks_for(cols, 256), nchunks), dim3(256), 0, s, in, w, rows, cols,
+                       part);
+    hipLaunchKernelGGL(qst::k_colsum_final, dim3(blocks_for(cols, 256)), dim3(256), 0, s, part, nchunks, cols, out);
+    hip_check(hipGetLastError(), "column sum launch");
+}
+
+// forward of n rows of X (BF16 [n][d]); s_out (nullable) gets scale*s + shift;
+// with y, the loss pieces (ds, sq) too
+void mlp_forward(qst_mlp* h, const uint16_t* X, int64_t n, float* s_out, const float* y, hipStream_t s)
+{
+    h->ensure(n);
+    const int N = static_cast<int>(n);
+    gemm<qst::kBiasGelu>(N, h->h1, h->d, X, h->d, h->W1b, h->d, nullptr, h->h1, h->theta + h->off_b1(), nullptr, h->Z1,
+                         h->H1, h->h1, s);
+    gemm<qst::kBiasGelu>(N, h->h2, h->h1, h->H1, h->h1, h->W2b, h->h1, nullptr, h->h2, h->theta + h->off_b2(), nullptr,
+                         h->Z2, h->H2, h->h2, s);
+    hipLaunchKernelGGL(qst::k_last_fwd, dim3(blocks_for(n, 4)), dim3(256), 0, s, h->H2, h->h2, h->theta + h->off_w3(),
+                       h->theta + h->off_b3(), n, h->out_scale, h->out_shift, s_out, y, h->ds, h->sq);
+    hip_check(hipGetLastError(), "last layer launch");
+}
+
+// gradients of the mean squared error into h->grad, loss into h->loss
+void mlp_backward(qst_mlp* h, const uint16_t* X, int64_t n, hipStream_t s)
+{
+    const int N = static_cast<int>(n);
+    float* g = h->grad;
+    // last layer: gw3 = H2^T ds, gb3 = sum ds, dZ2 = BF16(ds w3^T * gelu'(Z2))
+    colsum(h->H2, h->ds, n, h->h2, h->part, g + h->off_w3(), s);
+    colsum(nullptr, h->ds, n, 1, h->part, g + h->off_b3(), s);
+    hipLaunchKernelGGL(qst::k_last_bwd_dz, dim3(blocks_for(n * h->h2, 256)), dim3(256), 0, s, h->ds,
+                       h->theta + h->off_w3(), h->Z2, n, h->h2, h->dZ2);
+    // layer 2: gb2 = colsum dZ2, gW2 = dZ2^T H1, dZ1 = BF16((dZ2 W2) * gelu'(Z1))
+    colsum(h->dZ2, nullptr, n, h->h2, h->part, g + h->off_b2(), s);
+    hipLaunchKernelGGL(qst::k_transpose_bf16, dim3(blocks_for(h->h2, 32), blocks_for(n, 32)), dim3(256), 0, s, h->dZ2, N,
+                       h->h2, h->dZ2T);
+    hipLaunchKernelGGL(qst::k_transpose_bf16, dim3(blocks_for(h->h1, 32), blocks_for(n, 32)), dim3(256), 0, s, h->H1, N,
+                       h->h1, h->H1T);
+    gemm<qst::kStoreF32>(h->h2, h->h1, N, h->dZ2T, N, h->H1T, N, g + h->off_W2(), h->h1, nullptr, nullptr, nullptr,
+                         nullptr, 0, s);
+    hipLaunchKernelGGL(qst::k_transpose_bf16, dim3(blocks_for(h->h1, 32), blocks_for(h->h2, 32)), dim3(256), 0, s, h->W2b,
+                       h->h2, h->h1, h->W2T);
+    gemm<qst::kGeluGrad>(N, h->h1, h->h2, h->dZ2, h->h2, h->W2T, h->h2, nullptr, h->h1, nullptr, h->Z1, nullptr, h->dZ1,
+                         h->h1, s);
+    // layer 1: gb1 = colsum dZ1, gW1 = dZ1^T X
+    colsum(h->dZ1, nullptr, n, h->h1, h->part, g + h->off_b1(), s);
+    hipLaunchKernelGGL(qst::k_transpose_bf16, dim3(blocks_for(h->h1, 32), blocks_for(n, 32)), dim3(256), 0, s, h->dZ1, N,
+                       h->h1, h->dZ1T);
+    hipLaunchKernelGGL(qst::k_transpose_bf16, dim3(blocks_for(h->d, 32), blocks_for(n, 32)), dim3(256), 0, s, X, N, h->d,
+                       h->XT);
+    gemm<qst::kStoreF32>(h->h1, h->d, N, h->dZ1T, N, h->XT, N, g + h->off_W1(), h->d, nullptr, nullptr, nullptr, nullptr,
+                         0, s);
+    hipLaunchKernelGGL(qst::k_sum_f32, dim3(1), dim3(256), 0, s, h->sq, n, h->loss);
+    hip_check(hipGetLastError(), "MLP backward launch");
+}
+
+void check_mlp_batch(const qst_mlp* h, int64_t n)
+{
+    if (!h) fail(QST_ERR_INVALID, "NULL MLP handle");
+    if (n < 1) fail(QST_ERR_INVALID, "empty batch");
+    if (n % 32 != 0) fail(QST_ERR_INVALID, "training batch must be a multiple of 32 rows");
+    if (n > (1 << 24)) fail(QST_ERR_INVALID, "batch too large");
+}
+
+}  // namespace
+
+extern "C" {
+
+qst_status qst_mlp_create(int32_t d_in, int32_t h1, int32_t h2, int32_t device, qst_mlp** out)
+{
+    return guarded([&] {
+        if (!out) fail(QST_ERR_INVALID, "NULL output");
+        *out = nullptr;
+        if (d_in < 32 || d_in % 32 != 0) fail(QST_ERR_INVALID, "input width must be a positive multiple of 32");
+        if (h1 < 32 || h1 % 32 != 0 || h2 < 32 || h2 % 32 != 0 || h1 > 8192 || h2 > 8192)
+            fail(QST_ERR_INVALID, "hidden widths must be multiples of 32 in 32..8192");
+        int ndev = 0;
+        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        if (device < 0 || device >= ndev) fail(QST_ERR_INVALID, "bad device ordinal");
+        DeviceGuard g(device);
+        auto h = std::make_unique<qst_mlp>();
+        h->d = d_in;
+        h->h1 = h1;
+        h->h2 = h2;
+        h->device = device;
+        h->n_par = h->off_b3() + 1;
+        try {
+            h->theta = dev_alloc<float>(h->n_par);
+            h->grad = dev_alloc<float>(h->n_par);
+            h->m = dev_alloc<float>(h->n_par);
+            h->v = dev_alloc<float>(h->n_par);
+            h->W1b = dev_alloc<uint16_t>(static_cast<size_t>(h1) * d_in);
+            h->W2b = dev_alloc<uint16_t>(static_cast<size_t>(h2) * h1);
+            h->W2T = dev_alloc<uint16_t>(static_cast<size_t>(h2) * h1);
+            for (float* p : {h->theta, h->grad, h->m, h->v})
+                hip_check(hipMemset(p, 0, sizeof(float) * h->n_par), "zero MLP state");
+            mlp_refresh_bf16(h.get(), nullptr);
+            hip_check(hipDeviceSynchronize(), "MLP init");
+        } catch (...) {
+            h->free_all();
+            throw;
+        }
+        *out = h.release();
+    });
+}
+
+void qst_mlp_free(qst_mlp* h)
+{
+    if (!h) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    h->free_all();
+    (void)hipSetDevice(prev);
+    delete h;
+}
+
+int64_t qst_mlp_num_params(const qst_mlp* h) { return h ? h->n_par : -1; }
+
+qst_status qst_mlp_set_params(qst_mlp* h, const float* params, int64_t n, float out_scale, float out_shift)
+{
+    return guarded([&] {
+        if (!h || !params) fail(QST_ERR_INVALID, "NULL argument");
+        if (n != h->n_par) fail(QST_ERR_INVALID, "parameter count mismatch");
+        DeviceGuard g(h->device);
+        hip_check(hipMemcpy(h->theta, params, sizeof(float) * n, hipMemcpyHostToDevice), "copy parameters");
+        for (float* p : {h->m, h->v}) hip_check(hipMemset(p, 0, sizeof(float) * h->n_par), "reset Adam");
+        h->t = 0;
+        h->out_scale = out_scale;
+        h->out_shift = out_shift;
+        mlp_refresh_bf16(h, nullptr);
+        hip_check(hipDeviceSynchronize(), "set parameters");
+    });
+}
+
+qst_status qst_mlp_get_params(const qst_mlp* h, float* params, int64_t n)
+{
+    return guarded([&] {
+        if (!h || !params) fail(QST_ERR_INVALID, "NULL argument");
+        if (n != h->n_par) fail(QST_ERR_INVALID, "parameter count mismatch");
+        DeviceGuard g(h->device);
+        hip_check(hipDeviceSynchronize(), "sync");
+        hip_check(hipMemcpy(params, h->theta, sizeof(float) * n, hipMemcpyDeviceToHost), "copy parameters");
+    });
+}
+
+qst_status qst_mlp_gradients(qst_mlp* h, const uint16_t* x, const float* y, int64_t n, float* grad_host,
+                             float* loss_host, void* stream)
+{
+    return guarded([&] {
+        check_mlp_batch(h, n);
+        if (!x || !y) fail(QST_ERR_INVALID, "NULL batch");
+        DeviceGuard g(h->device);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        mlp_forward(h, x, n, nullptr, y, s);
+        mlp_backward(h, x, n, s);
+        hip_check(hipStreamSynchronize(s), "gradients synchronize");
+        if (grad_host)
+            hip_check(hipMemcpy(grad_host, h->grad, sizeof(float) * h->n_par, hipMemcpyDeviceToHost), "copy gradients");
+        if (loss_host) {
+            float l = 0.0f;
+            hip_check(hipMemcpy(&l, h->loss, sizeof(float), hipMemcpyDeviceToHost), "copy loss");
+            *loss_host = l / static_cast<float>(n);
+        }
+    });
+}
+
+qst_status qst_mlp_train_step(qst_mlp* h, const uint16_t* x, const float* y, int64_t n, float lr, float* loss_host,
+                              void* stream)
+{
+    return guarded([&] {
+        check_mlp_batch(h, n);
+        if (!x || !y) fail(QST_ERR_INVALID, "NULL batch");
+        if (!(lr > 0.0f)) fail(QST_ERR_INVALID, "learning rate must be positive");
+        DeviceGuard g(h->device);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        mlp_forward(h, x, n, nullptr, y, s);
+        mlp_backward(h, x, n, s);
+        h->t += 1;
+        const double b1 = 0.9, b2 = 0.999;
+        const float bc1 = static_cast<float>(1.0 - std::pow(b1, static_cast<double>(h->t)));
+        const float bc2 = static_cast<float>(1.0 - std::pow(b2, static_cast<double>(h->t)));
+        hipLaunchKernelGGL(qst::k_adam, dim3(blocks_for(h->n_par, 256)), dim3(256), 0, s, h->theta, h->grad, h->m, h->v,
+                           h->n_par, lr, 0.9f, 0.999f, 1e-8f, bc1, bc2);
+        hip_check(hipGetLastError(), "Adam launch");
+        mlp_refresh_bf16(h, s);
+        if (loss_host) {
+            hip_check(hipStreamSynchronize(s), "train synchronize");
+            float l = 0.0f;
+            hip_check(hipMemcpy(&l, h->loss, sizeof(float), hipMemcpyDeviceToHost), "copy loss");
+            *loss_host = l / static_cast<float>(n);
+        }
+    });
+}
+
+qst_status qst_mlp_predict(qst_mlp* h, const uint16_t* x, int64_t n, float* out, void* stream)
+{
+    return guarded([&] {
+        if (!h || !x || !out) fail(QST_ERR_INVALID, "NULL argument");
+        if (n < 1) fail(QST_ERR_INVALID, "empty batch");
+        DeviceGuard g(h->device);
+        mlp_forward(h, x, n, out, nullptr, static_cast<hipStream_t>(stream));
+    });
+}
+
+qst_status qst_mlp_surrogate(const qst_mlp* h, qst_surrogate* out)
+{
+    return guarded([&] {
+        if (!h || !out) fail(QST_ERR_INVALID, "NULL argument");
+        out->h1 = h->h1;
+        out->h2 = h->h2;
+        out->W1 = h->W1b;
+        out->b1 = h->theta + h->off_b1();
+        out->W2 = h->W2b;
+        out->b2 = h->theta + h->off_b2();
+        out->w3 = h->theta + h->off_w3();
+        out->b3 = 0.0f;   // read from the device copy by the delayed-acceptance path
+        out->out_scale = h->out_scale;
+        out->out_shift = h->out_shift;
+        out->model = const_cast<qst_mlp*>(h);
     });
 }
 

@@ -38,7 +38,7 @@ class _ProblemDesc(C.Structure):
 class _Surrogate(C.Structure):
     _fields_ = [("h1", C.c_int32), ("h2", C.c_int32), ("W1", C.c_void_p), ("b1", C.c_void_p),
                 ("W2", C.c_void_p), ("b2", C.c_void_p), ("w3", C.c_void_p), ("b3", C.c_float),
-                ("out_scale", C.c_float), ("out_shift", C.c_float)]
+                ("out_scale", C.c_float), ("out_shift", C.c_float), ("model", C.c_void_p)]
 
 
 class _RunDesc(C.Structure):
@@ -85,13 +85,25 @@ def lib():
         L.qst_get_launch_shape.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.qst_list_launch_shapes.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
                                              C.POINTER(C.c_int32)]
+        L.qst_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(vp)]
+        L.qst_mlp_free.argtypes = [vp]
+        L.qst_mlp_free.restype = None
+        L.qst_mlp_num_params.argtypes = [vp]
+        L.qst_mlp_num_params.restype = C.c_int64
+        L.qst_mlp_set_params.argtypes = [vp, C.POINTER(C.c_float), C.c_int64, C.c_float, C.c_float]
+        L.qst_mlp_get_params.argtypes = [vp, C.POINTER(C.c_float), C.c_int64]
+        L.qst_mlp_gradients.argtypes = [vp, vp, vp, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float), vp]
+        L.qst_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.POINTER(C.c_float), vp]
+        L.qst_mlp_predict.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.qst_mlp_surrogate.argtypes = [vp, C.POINTER(_Surrogate)]
         L.qst_free_problem.argtypes = [vp]
         L.qst_free_problem.restype = None
         L.qst_last_error.restype = C.c_char_p
         L.qst_version.restype = C.c_char_p
         for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state",
                   "qst_loglik", "qst_acf", "qst_set_launch_shape", "qst_get_launch_shape",
-                  "qst_list_launch_shapes"):
+                  "qst_list_launch_shapes", "qst_mlp_create", "qst_mlp_set_params", "qst_mlp_get_params",
+                  "qst_mlp_gradients", "qst_mlp_train_step", "qst_mlp_predict", "qst_mlp_surrogate"):
             getattr(L, f).restype = C.c_int
         _lib = L
         _install_tuned_shapes()
@@ -231,6 +243,74 @@ class Problem:
         _check(lib().qst_loglik(self._h, C.c_void_p(rho_dev.data_ptr()), n, C.c_void_p(out_dev.data_ptr()),
                                 _PATH[path], _PREC[precision],
                                 stream if stream is not None else current_stream()))
+
+
+class Mlp:
+    """The MLP surrogate (qst_mlp_*): parameters, training step, prediction."""
+
+    def __init__(self, d_in, h1=512, h2=512, device=0):
+        h = C.c_void_p()
+        _check(lib().qst_mlp_create(d_in, h1, h2, device, C.byref(h)))
+        self._h = h
+        self.d, self.h1, self.h2 = d_in, h1, h2
+        self.n_params = int(lib().qst_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qst_mlp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat, out_scale=1.0, out_shift=0.0):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().qst_mlp_set_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size,
+                                        out_scale, out_shift))
+
+    def get_params(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().qst_mlp_get_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    @staticmethod
+    def _bf16(x):
+        import torch
+        return x.to(torch.bfloat16).contiguous()
+
+    def gradients(self, x, y):
+        """x: torch device tensor [n, d] (any float dtype; rounded to BF16), y [n]."""
+        import torch
+        xb = self._bf16(x)
+        yf = y.to(torch.float32).contiguous()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().qst_mlp_gradients(self._h, C.c_void_p(xb.data_ptr()), C.c_void_p(yf.data_ptr()), xb.shape[0],
+                                       g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss), current_stream()))
+        return g, loss.value
+
+    def train_step(self, x_bf16, y_f32, lr, want_loss=False):
+        loss = C.c_float()
+        _check(lib().qst_mlp_train_step(self._h, C.c_void_p(x_bf16.data_ptr()), C.c_void_p(y_f32.data_ptr()),
+                                        x_bf16.shape[0], lr, C.byref(loss) if want_loss else None,
+                                        current_stream()))
+        return loss.value if want_loss else None
+
+    def predict(self, x):
+        import torch
+        xb = self._bf16(x)
+        out = torch.empty(xb.shape[0], dtype=torch.float32, device=xb.device)
+        _check(lib().qst_mlp_predict(self._h, C.c_void_p(xb.data_ptr()), xb.shape[0], C.c_void_p(out.data_ptr()),
+                                     current_stream()))
+        return out
+
+    def surrogate(self):
+        s = _Surrogate()
+        _check(lib().qst_mlp_surrogate(self._h, C.byref(s)))
+        return s
 
 
 def set_launch_shape(n_qubits, team, workgroup):
