@@ -133,6 +133,15 @@ typedef struct {
     int32_t record_every;
     int32_t record_chains;
     double* record_buf;
+    /* optional training pairs for the surrogate (plain pCN only): every
+     * pair_every steps, for the first pair_chains chains, the proposal y'
+     * (BF16 bits, zero padded to 2D^2+D rounded up to a multiple of 32) and its
+     * log L (DEVICE buffers, caller-owned, [pair_chains][n_steps / pair_every]
+     * rows) */
+    int32_t pair_every;
+    int32_t pair_chains;
+    uint16_t* pair_x;
+    double* pair_ll;
     void* stream;            /* hipStream_t the work is queued on (NULL = default stream) */
 } qst_run_desc;
 

@@ -80,6 +80,13 @@ struct ChainArgs {
     int32_t record_every;
     int32_t record_chains;
     double* rec;
+    // training pairs for the surrogate: every pair_every steps, the proposal
+    // y' (BF16, zero padded to pair_width) and its log L, first pair_chains chains
+    int32_t pair_every;
+    int32_t pair_chains;
+    int32_t pair_width;
+    uint16_t* pair_x;
+    double* pair_ll;
 };
 
 // How p = Tr(Lambda rho) is formed inside the chain step.
@@ -707,10 +714,20 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
 #pragma unroll
         for (int e = 0; e < S::NYL; ++e) {
             const int i = lane + G * e;
-            if (i < d) ybuf[i] = a * y[e] + beta * ybuf[i];
+            if (i < d) ybuf[i] = __builtin_fma(beta, ybuf[i], a * y[e]);
         }
         __syncthreads();
         const double llp = evaluate();
+        if (A.pair_every > 0 && live && chain < A.pair_chains && (t + 1) % A.pair_every == 0) {
+            const int64_t n_pair = A.n_steps / A.pair_every;
+            const int64_t slot = (t + 1) / A.pair_every - 1;
+            uint16_t* dst = A.pair_x + (chain * n_pair + slot) * A.pair_width;
+            for (int i = lane; i < A.pair_width; i += G) {
+                const float v = i < d ? static_cast<float>(ybuf[i]) : 0.0f;
+                dst[i] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
+            }
+            if (lane == 0) A.pair_ll[chain * n_pair + slot] = llp;
+        }
         const double logu = fast_log(misc[0], logtab);
         const double delta = llp - ll;
         const bool accept = logu < delta;
@@ -739,7 +756,7 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
 #pragma unroll
             for (int e = 0; e < S::NPL; ++e) {
                 s1[e] += rc[e];
-                s2[e] += rc[e] * rc[e];
+                s2[e] = __builtin_fma(rc[e], rc[e], s2[e]);
             }
             ++nst;
         }

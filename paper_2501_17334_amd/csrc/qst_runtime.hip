@@ -18,6 +18,7 @@
 #include "acf_kernel.hpp"
 #include "batch_kernel.hpp"
 #include "chain_kernel.hpp"
+#include "da_kernel.hpp"
 #include "mlp_kernels.hpp"
 #include "pool_kernel.hpp"
 
@@ -346,6 +347,43 @@ struct qst_problem {
     int32_t* accw = nullptr;
     int64_t *nst = nullptr, *nacc = nullptr, *nnear = nullptr;
     hipStream_t last_stream = nullptr;
+    // delayed acceptance (allocated on first use)
+    int64_t da_R = 0;
+    double *s_cur = nullptr, *yprop = nullptr, *u_mh = nullptr, *u_da = nullptr;
+    int64_t* n_stage1 = nullptr;
+    uint16_t* xb = nullptr;
+    float* smlp = nullptr;
+    int32_t *surv = nullptr, *n_surv = nullptr;
+
+    int da_width() const { return (d + 31) / 32 * 32; }
+    void free_da()
+    {
+        dev_free(s_cur);
+        dev_free(yprop);
+        dev_free(u_mh);
+        dev_free(u_da);
+        dev_free(n_stage1);
+        dev_free(xb);
+        dev_free(smlp);
+        dev_free(surv);
+        dev_free(n_surv);
+        da_R = 0;
+    }
+    void ensure_da()
+    {
+        if (da_R == R) return;
+        free_da();
+        s_cur = dev_alloc<double>(R);
+        yprop = dev_alloc<double>(static_cast<size_t>(R) * d);
+        u_mh = dev_alloc<double>(R);
+        u_da = dev_alloc<double>(R);
+        n_stage1 = dev_alloc<int64_t>(R);
+        xb = dev_alloc<uint16_t>(static_cast<size_t>(R) * da_width());
+        smlp = dev_alloc<float>(R);
+        surv = dev_alloc<int32_t>(R);
+        n_surv = dev_alloc<int32_t>(1);
+        da_R = R;
+    }
 
     void free_state()
     {
@@ -359,6 +397,7 @@ struct qst_problem {
         dev_free(nst);
         dev_free(nacc);
         dev_free(nnear);
+        free_da();
         R = 0;
     }
     void alloc_state(int64_t n)
@@ -393,11 +432,18 @@ void validate_run(const qst_problem* p, const qst_run_desc& r)
         fail(QST_ERR_INVALID, "negative trace/record sizes");
     if (r.record_every > 0 && r.record_chains > 0 && !r.record_buf)
         fail(QST_ERR_INVALID, "record_buf is NULL");
+    if (r.pair_every < 0 || r.pair_chains < 0) fail(QST_ERR_INVALID, "negative pair-recorder sizes");
+    if (r.pair_every > 0 && r.pair_chains > 0 && (!r.pair_x || !r.pair_ll))
+        fail(QST_ERR_INVALID, "pair buffers are NULL");
+    if (r.pair_every > 0 && r.surrogate) fail(QST_ERR_UNSUPPORTED, "the pair recorder runs with plain pCN");
     if (r.resume) {
         if (!p->have_run) fail(QST_ERR_STATE, "resume requested before any run of this handle");
         if (r.n_chains != p->R) fail(QST_ERR_INVALID, "resume with a different n_chains");
     }
-    if (r.surrogate) fail(QST_ERR_UNSUPPORTED, "delayed acceptance is not available in this build");
+    if (r.surrogate) {
+        if (!r.surrogate->model) fail(QST_ERR_INVALID, "surrogate has no model (use qst_mlp_surrogate)");
+        if (p->path != QST_PATH_KRON) fail(QST_ERR_UNSUPPORTED, "delayed acceptance uses the FP64 Kronecker path");
+    }
 }
 
 }  // namespace
@@ -470,6 +516,8 @@ void qst_free_problem(qst_problem* p)
 
 namespace {
 
+void launch_da(qst_problem* p, const qst_run_desc& r, hipStream_t s);   // delayed acceptance (below)
+
 void prepare_state(qst_problem* p, const qst_run_desc& r)
 {
     if (!r.resume) {
@@ -516,6 +564,11 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
     a.record_every = r.record_every;
     a.record_chains = r.record_chains;
     a.rec = r.record_buf;
+    a.pair_every = r.pair_every;
+    a.pair_chains = r.pair_chains;
+    a.pair_width = p->da_width();
+    a.pair_x = r.pair_x;
+    a.pair_ll = r.pair_ll;
     return a;
 }
 
@@ -656,12 +709,16 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
         DeviceGuard g(dev);
         hipStream_t s = static_cast<hipStream_t>(runs[0].stream);
         for (int i = 0; i < n_problems; ++i) prepare_state(problems[i], runs[i]);
-        if (n_problems == 1) {
+        if (n_problems == 1 && runs[0].surrogate) {
+            launch_da(problems[0], runs[0], s);
+        } else if (n_problems == 1) {
             qst_problem* p = problems[0];
             const qst::ChainArgs a = make_args(p, runs[0]);
             launch_chains(p->Q, current_shape(p->Q), p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
                           static_cast<int>(p->precision), a, s);
         } else {
+            for (int i = 0; i < n_problems; ++i)
+                if (runs[i].surrogate) fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs one problem per call");
             launch_batch(problems, n_problems, runs, s);
         }
         for (int i = 0; i < n_problems; ++i) {
@@ -671,7 +728,17 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
         }
         if (stats) {
             hip_check(hipStreamSynchronize(s), "run synchronize");
-            for (int i = 0; i < n_problems; ++i) stats[i] = collect_stats(problems[i], runs[i]);
+            for (int i = 0; i < n_problems; ++i) {
+                stats[i] = collect_stats(problems[i], runs[i]);
+                if (runs[i].surrogate) {
+                    std::vector<int64_t> s1(problems[i]->R);
+                    hip_check(hipMemcpy(s1.data(), problems[i]->n_stage1, sizeof(int64_t) * s1.size(),
+                                        hipMemcpyDeviceToHost), "stats");
+                    int64_t tot = 0;
+                    for (int64_t v : s1) tot += v;
+                    stats[i].stage1_passed = tot;
+                }
+            }
         }
     });
 }
@@ -1146,3 +1213,100 @@ qst_status qst_mlp_surrogate(const qst_mlp* h, qst_surrogate* out)
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Delayed acceptance: the per-step launch sequence
+// ===========================================================================
+namespace {
+
+// Team shape of the delayed-acceptance kernels per qubit count (the tuned
+// single-problem defaults).
+Shape da_shape(int Q) { return Shape{Q == 1 ? 8 : Q == 2 ? 16 : Q == 3 ? 32 : Q == 4 ? 64 : Q == 5 ? 256 : 512,
+                                     Q <= 3 ? 64 : Q == 4 ? 256 : Q == 5 ? 256 : 512}; }
+
+template <typename T>
+void fill_zero(T* p, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((qst::k_fill_zero<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+    hip_check(hipGetLastError(), "clear");
+}
+
+template <int Q, int G, int WG>
+void da_steps(qst_problem* p, const qst_run_desc& r, qst_mlp* net, qst::DaArgs P, hipStream_t s)
+{
+    using Dm = qst::Dims<Q>;
+    using S = qst::TeamShape<Q, G>;
+    const int64_t teams = WG / G;
+    const unsigned blocks = static_cast<unsigned>((p->R + teams - 1) / teams);
+    const size_t lds_prop = (2 * qst::kLogTableSize + static_cast<size_t>(teams) * (Dm::d + 4)) * sizeof(double);
+    const size_t lds_exact = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q>::kDoubles) * sizeof(double);
+    static bool attr_done = false;
+    if (!attr_done) {
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_da_propose<Q, G, WG>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_prop)),
+                  "hipFuncSetAttribute");
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_da_exact<Q, G, WG>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_exact)),
+                  "hipFuncSetAttribute");
+        attr_done = true;
+    }
+    for (int64_t t = 0; t < r.n_steps; ++t) {
+        P.j = p->step + 1 + t;
+        P.t = t;
+        hipLaunchKernelGGL((qst::k_da_propose<Q, G, WG>), dim3(blocks), dim3(WG), lds_prop, s, P);
+        mlp_forward(net, p->xb, p->R, p->smlp, nullptr, s);
+        hipLaunchKernelGGL(qst::k_zero_counter, dim3(1), dim3(1), 0, s, p->n_surv);
+        hipLaunchKernelGGL((qst::k_da_stage1<Q>), dim3(static_cast<unsigned>((p->R + 3) / 4)), dim3(256), 0, s, P);
+        hipLaunchKernelGGL((qst::k_da_exact<Q, G, WG>), dim3(blocks), dim3(WG), lds_exact, s, P);
+        hip_check(hipGetLastError(), "delayed-acceptance step launch");
+    }
+}
+
+void launch_da(qst_problem* p, const qst_run_desc& r, hipStream_t s)
+{
+    qst_mlp* net = r.surrogate->model;
+    if (net->device != p->device) fail(QST_ERR_INVALID, "surrogate lives on another device");
+    if (net->d != p->da_width())
+        fail(QST_ERR_INVALID, "surrogate input width must be 2D^2+D rounded up to a multiple of 32");
+    p->ensure_da();
+    const Shape sh = da_shape(p->Q);
+    // step 0 (or the resumed state) by the plain kernel, then s(y) of the current states
+    if (!r.resume) {
+        qst_run_desc r0 = r;
+        r0.n_steps = 0;
+        r0.surrogate = nullptr;
+        qst::ChainArgs a0 = make_args(p, r0);
+        launch_chains(p->Q, sh, qst::kPathKron, qst::kPrecF64, a0, s);
+    }
+    const int dp = p->da_width();
+    hipLaunchKernelGGL(qst::k_rows_to_bf16, dim3(blocks_for(p->R * dp, 256)), dim3(256), 0, s, p->x, p->R, p->d, dp,
+                       p->xb);
+    mlp_forward(net, p->xb, p->R, p->smlp, nullptr, s);
+    hipLaunchKernelGGL(qst::k_f32_to_f64, dim3(blocks_for(p->R, 256)), dim3(256), 0, s, p->smlp, p->R, p->s_cur);
+    fill_zero(p->n_stage1, p->R, s);
+    fill_zero(p->nacc, p->R, s);
+    fill_zero(p->nnear, p->R, s);
+    hip_check(hipGetLastError(), "delayed-acceptance setup");
+    qst::DaArgs P{};
+    P.A = make_args(p, r);
+    P.s_cur = p->s_cur;
+    P.n_stage1 = p->n_stage1;
+    P.yprop = p->yprop;
+    P.xb = p->xb;
+    P.dp = dp;
+    P.smlp = p->smlp;
+    P.u_mh = p->u_mh;
+    P.u_da = p->u_da;
+    P.surv = p->surv;
+    P.n_surv = p->n_surv;
+    switch (p->Q) {
+        case 1: return da_steps<1, 8, 64>(p, r, net, P, s);
+        case 2: return da_steps<2, 16, 64>(p, r, net, P, s);
+        case 3: return da_steps<3, 32, 64>(p, r, net, P, s);
+        case 4: return da_steps<4, 64, 256>(p, r, net, P, s);
+        case 5: return da_steps<5, 256, 256>(p, r, net, P, s);
+        default: return da_steps<6, 512, 512>(p, r, net, P, s);
+    }
+}
+
+}  // namespace

@@ -49,7 +49,8 @@ class _RunDesc(C.Structure):
                 ("surrogate", C.POINTER(_Surrogate)), ("trace_chains", C.c_int32),
                 ("trace_llprop", C.c_void_p), ("trace_logu", C.c_void_p), ("trace_accept", C.c_void_p),
                 ("record_every", C.c_int32), ("record_chains", C.c_int32), ("record_buf", C.c_void_p),
-                ("stream", C.c_void_p)]
+                ("pair_every", C.c_int32), ("pair_chains", C.c_int32), ("pair_x", C.c_void_p),
+                ("pair_ll", C.c_void_p), ("stream", C.c_void_p)]
 
 
 class _RunStats(C.Structure):
@@ -186,21 +187,33 @@ class Problem:
         except Exception:
             pass
 
-    def _run_desc(self, cfg: RunConfig, trace=None, record=None, stream=None):
+    @property
+    def pair_width(self):
+        """Width of a surrogate input row: 2D^2+D rounded up to a multiple of 32."""
+        return (self.d + 31) // 32 * 32
+
+    def _run_desc(self, cfg: RunConfig, trace=None, record=None, stream=None, surrogate=None, pairs=None):
         trace = trace or {}
         record = record or {}
+        pairs = pairs or {}
+        self._sur = C.pointer(surrogate) if surrogate is not None else None
         return _RunDesc(cfg.n_chains, cfg.n_steps, cfg.thin, cfg.burn_in, cfg.beta0, cfg.adapt_every,
                         cfg.adapt_lo, cfg.adapt_hi, cfg.adapt_factor, cfg.adapt_until, cfg.seed,
-                        1 if cfg.resume else 0, None, trace.get("chains", 0),
+                        1 if cfg.resume else 0, self._sur, trace.get("chains", 0),
                         _dptr(trace.get("llprop")), _dptr(trace.get("logu")),
                         _dptr(trace.get("accept")), record.get("every", 0), record.get("chains", 0),
-                        _dptr(record.get("buf")), stream if stream is not None else current_stream())
+                        _dptr(record.get("buf")), pairs.get("every", 0), pairs.get("chains", 0),
+                        _dptr(pairs.get("x")), _dptr(pairs.get("ll")),
+                        stream if stream is not None else current_stream())
 
-    def run(self, cfg: RunConfig, trace=None, record=None, stats=True, stream=None):
+    def run(self, cfg: RunConfig, trace=None, record=None, stats=True, stream=None, surrogate=None, pairs=None):
         """qst_run_chains on this problem alone.  trace: dict(chains=k, llprop=,
         logu=, accept=) torch device tensors [k, n_steps]; record: dict(every=,
-        chains=, buf=) torch device tensor [chains, n_steps // every, D, D]."""
-        rd = _run_desc(self, cfg, trace, record, stream)
+        chains=, buf=) torch device tensor [chains, n_steps // every, D, D];
+        surrogate: an Mlp.surrogate() (delayed acceptance); pairs: dict(every=,
+        chains=, x= bfloat16 [chains, n_steps // every, pair_width], ll= float64
+        [chains, n_steps // every])."""
+        rd = self._run_desc(cfg, trace, record, stream, surrogate, pairs)
         arr = (C.c_void_p * 1)(self._h)
         st = _RunStats()
         _check(lib().qst_run_chains(arr, 1, C.byref(rd), C.byref(st) if stats else None))
