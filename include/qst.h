@@ -136,8 +136,9 @@ typedef struct {
     /* optional training pairs for the surrogate (plain pCN only): every
      * pair_every steps, for the first pair_chains chains, the proposal y'
      * (BF16 bits, zero padded to 2D^2+D rounded up to a multiple of 32) and its
-     * log L (DEVICE buffers, caller-owned, [pair_chains][n_steps / pair_every]
-     * rows) */
+     * log L (DEVICE buffers, caller-owned, n_steps / pair_every * pair_chains
+     * rows, row = slot * pair_chains + chain, so consecutive rows are
+     * different chains) */
     int32_t pair_every;
     int32_t pair_chains;
     uint16_t* pair_x;
@@ -239,6 +240,15 @@ qst_status qst_mlp_train_step(qst_mlp* h, const uint16_t* x, const float* y, int
                               void* stream);
 /* out (DEVICE FP32 [n]) = out_scale * s(x) + out_shift */
 qst_status qst_mlp_predict(qst_mlp* h, const uint16_t* x, int64_t n, float* out, void* stream);
+/* training targets: y[i] = (ll[i] - mean) / sd over the n DEVICE values ll
+ * (FP64) into DEVICE FP32 y; mean and sd (population) to the host.
+ * QST_ERR_INVALID if a value is not finite or all are equal. */
+qst_status qst_mlp_targets(const double* ll, int64_t n, float* y, double* mean, double* sd, void* stream);
+/* rows of a training set in a given order: xo[k] = x[idx[k]] (width BF16
+ * values per row), yo[k] = y[idx[k]]; all DEVICE; idx entries must be valid
+ * row indices of x and y (not checked). */
+qst_status qst_gather_rows(const uint16_t* x, int32_t width, const float* y, const int64_t* idx, int64_t n,
+                           uint16_t* xo, float* yo, void* stream);
 /* the frozen surrogate for qst_run_desc.surrogate (pointers into h; valid while h lives) */
 qst_status qst_mlp_surrogate(const qst_mlp* h, qst_surrogate* out);
 

@@ -81,7 +81,8 @@ struct ChainArgs {
     int32_t record_chains;
     double* rec;
     // training pairs for the surrogate: every pair_every steps, the proposal
-    // y' (BF16, zero padded to pair_width) and its log L, first pair_chains chains
+    // y' (BF16, zero padded to pair_width) and its log L of the first
+    // pair_chains chains, row slot * pair_chains + chain
     int32_t pair_every;
     int32_t pair_chains;
     int32_t pair_width;
@@ -719,14 +720,14 @@ __device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tabl
         __syncthreads();
         const double llp = evaluate();
         if (A.pair_every > 0 && live && chain < A.pair_chains && (t + 1) % A.pair_every == 0) {
-            const int64_t n_pair = A.n_steps / A.pair_every;
-            const int64_t slot = (t + 1) / A.pair_every - 1;
-            uint16_t* dst = A.pair_x + (chain * n_pair + slot) * A.pair_width;
+            const int64_t slot = (t + 1) / A.pair_every - 1;   // rows are slot-major: [slot][chain]
+            const int64_t row = slot * A.pair_chains + chain;
+            uint16_t* dst = A.pair_x + row * A.pair_width;
             for (int i = lane; i < A.pair_width; i += G) {
                 const float v = i < d ? static_cast<float>(ybuf[i]) : 0.0f;
                 dst[i] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
             }
-            if (lane == 0) A.pair_ll[chain * n_pair + slot] = llp;
+            if (lane == 0) A.pair_ll[row] = llp;
         }
         const double logu = fast_log(misc[0], logtab);
         const double delta = llp - ll;

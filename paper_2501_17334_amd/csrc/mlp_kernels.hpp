@@ -224,6 +224,65 @@ __global__ __launch_bounds__(256) void k_sum_f32(const float* __restrict__ in, i
     }
 }
 
+// Mean, variance and count of non-finite values of n doubles, fixed order
+// (one workgroup): out = {mean, var, nonfinite}.
+__global__ __launch_bounds__(256) void k_moments_f64(const double* __restrict__ x, int64_t n, double* __restrict__ out)
+{
+    __shared__ double ps[256], pq[256], pb[256];
+    double s = 0.0, bad = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double v = x[i];
+        if (isfinite(v)) s += v;
+        else bad += 1.0;
+    }
+    ps[threadIdx.x] = s;
+    pb[threadIdx.x] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int t = 0; t < 256; ++t) {
+            a += ps[t];
+            b += pb[t];
+        }
+        ps[0] = a / static_cast<double>(n);
+        pb[0] = b;
+    }
+    __syncthreads();
+    const double mean = ps[0];
+    double q = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double v = x[i] - mean;
+        if (isfinite(v)) q += v * v;
+    }
+    pq[threadIdx.x] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        for (int t = 0; t < 256; ++t) a += pq[t];
+        out[0] = mean;
+        out[1] = a / static_cast<double>(n);
+        out[2] = pb[0];
+    }
+}
+
+__global__ void k_standardise(const double* __restrict__ x, int64_t n, double mean, double sd, float* __restrict__ y)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = static_cast<float>((x[i] - mean) / sd);
+}
+
+// Row gather: xo[k] = x[idx[k]] (width BF16 values), yo[k] = y[idx[k]].
+__global__ void k_gather_rows(const uint16_t* __restrict__ x, int width, const float* __restrict__ y,
+                              const int64_t* __restrict__ idx, int64_t n, uint16_t* __restrict__ xo,
+                              float* __restrict__ yo)
+{
+    const int64_t k = blockIdx.x;
+    if (k >= n) return;
+    const int64_t r = idx[k];
+    for (int i = threadIdx.x; i < width; i += blockDim.x) xo[k * width + i] = x[r * width + i];
+    if (threadIdx.x == 0) yo[k] = y[r];
+}
+
 // Adam (Kingma & Ba 2015) on the flat FP32 parameter array.
 __global__ void k_adam(float* __restrict__ theta, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, int64_t n, float lr, float beta1, float beta2, float eps,

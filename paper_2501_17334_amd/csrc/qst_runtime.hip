@@ -1194,6 +1194,48 @@ qst_status qst_mlp_predict(qst_mlp* h, const uint16_t* x, int64_t n, float* out,
     });
 }
 
+qst_status qst_mlp_targets(const double* ll, int64_t n, float* y, double* mean, double* sd, void* stream)
+{
+    return guarded([&] {
+        if (!ll || !y || !mean || !sd) fail(QST_ERR_INVALID, "NULL argument");
+        if (n < 2) fail(QST_ERR_INVALID, "need at least two targets");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        double* mom = dev_alloc<double>(3);
+        double host[3] = {0.0, 0.0, 0.0};
+        try {
+            hipLaunchKernelGGL(qst::k_moments_f64, dim3(1), dim3(256), 0, s, ll, n, mom);
+            hip_check(hipGetLastError(), "target moments");
+            hip_check(hipStreamSynchronize(s), "target moments");
+            hip_check(hipMemcpy(host, mom, sizeof(host), hipMemcpyDeviceToHost), "target moments");
+        } catch (...) {
+            dev_free(mom);
+            throw;
+        }
+        dev_free(mom);
+        if (host[2] != 0.0) fail(QST_ERR_INVALID, "non-finite training target");
+        const double sdv = std::sqrt(host[1]);
+        if (!(sdv > 0.0)) fail(QST_ERR_INVALID, "constant training targets");
+        hipLaunchKernelGGL(qst::k_standardise, dim3(blocks_for(n, 256)), dim3(256), 0, s, ll, n, host[0], sdv, y);
+        hip_check(hipGetLastError(), "standardise");
+        *mean = host[0];
+        *sd = sdv;
+    });
+}
+
+qst_status qst_gather_rows(const uint16_t* x, int32_t width, const float* y, const int64_t* idx, int64_t n,
+                           uint16_t* xo, float* yo, void* stream)
+{
+    return guarded([&] {
+        if (!x || !y || !idx || !xo || !yo) fail(QST_ERR_INVALID, "NULL argument");
+        if (n < 0 || width < 1) fail(QST_ERR_INVALID, "bad sizes");
+        if (n == 0) return;
+        if (n > 0x7fffffff) fail(QST_ERR_INVALID, "too many rows");
+        hipLaunchKernelGGL(qst::k_gather_rows, dim3(static_cast<unsigned>(n)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), x, width, y, idx, n, xo, yo);
+        hip_check(hipGetLastError(), "gather launch");
+    });
+}
+
 qst_status qst_mlp_surrogate(const qst_mlp* h, qst_surrogate* out)
 {
     return guarded([&] {

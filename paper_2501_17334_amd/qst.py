@@ -97,6 +97,8 @@ def lib():
         L.qst_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.POINTER(C.c_float), vp]
         L.qst_mlp_predict.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.qst_mlp_surrogate.argtypes = [vp, C.POINTER(_Surrogate)]
+        L.qst_mlp_targets.argtypes = [vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
+        L.qst_gather_rows.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, vp, vp, vp]
         L.qst_free_problem.argtypes = [vp]
         L.qst_free_problem.restype = None
         L.qst_last_error.restype = C.c_char_p
@@ -104,7 +106,8 @@ def lib():
         for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state",
                   "qst_loglik", "qst_acf", "qst_set_launch_shape", "qst_get_launch_shape",
                   "qst_list_launch_shapes", "qst_mlp_create", "qst_mlp_set_params", "qst_mlp_get_params",
-                  "qst_mlp_gradients", "qst_mlp_train_step", "qst_mlp_predict", "qst_mlp_surrogate"):
+                  "qst_mlp_gradients", "qst_mlp_train_step", "qst_mlp_predict", "qst_mlp_surrogate",
+                  "qst_mlp_targets", "qst_gather_rows"):
             getattr(L, f).restype = C.c_int
         _lib = L
         _install_tuned_shapes()
@@ -305,11 +308,15 @@ class Mlp:
                                        g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss), current_stream()))
         return g, loss.value
 
-    def train_step(self, x_bf16, y_f32, lr, want_loss=False):
+    def train_step(self, x_bf16, y_f32, lr, want_loss=False, rows=None, offset=0):
+        """One Adam step on rows [offset, offset + rows) of device tensors
+        x_bf16 [N, d] (bfloat16) and y_f32 [N] (pointer arithmetic only)."""
+        n = x_bf16.shape[0] if rows is None else rows
+        xp = x_bf16.data_ptr() + offset * x_bf16.shape[1] * 2
+        yp = y_f32.data_ptr() + offset * 4
         loss = C.c_float()
-        _check(lib().qst_mlp_train_step(self._h, C.c_void_p(x_bf16.data_ptr()), C.c_void_p(y_f32.data_ptr()),
-                                        x_bf16.shape[0], lr, C.byref(loss) if want_loss else None,
-                                        current_stream()))
+        _check(lib().qst_mlp_train_step(self._h, C.c_void_p(xp), C.c_void_p(yp), n, lr,
+                                        C.byref(loss) if want_loss else None, current_stream()))
         return loss.value if want_loss else None
 
     def predict(self, x):
@@ -324,6 +331,21 @@ class Mlp:
         s = _Surrogate()
         _check(lib().qst_mlp_surrogate(self._h, C.byref(s)))
         return s
+
+
+def standardise_targets(ll_dev, y_dev, stream=None):
+    """qst_mlp_targets: y = (ll - mean) / sd on the device; returns (mean, sd)."""
+    mean, sd = C.c_double(), C.c_double()
+    _check(lib().qst_mlp_targets(C.c_void_p(ll_dev.data_ptr()), ll_dev.numel(), C.c_void_p(y_dev.data_ptr()),
+                                 C.byref(mean), C.byref(sd), stream if stream is not None else current_stream()))
+    return mean.value, sd.value
+
+
+def gather_rows(x, y, idx, xo, yo, stream=None):
+    """qst_gather_rows on torch device tensors (idx int64)."""
+    _check(lib().qst_gather_rows(C.c_void_p(x.data_ptr()), x.shape[1], C.c_void_p(y.data_ptr()),
+                                 C.c_void_p(idx.data_ptr()), idx.numel(), C.c_void_p(xo.data_ptr()),
+                                 C.c_void_p(yo.data_ptr()), stream if stream is not None else current_stream()))
 
 
 def set_launch_shape(n_qubits, team, workgroup):
