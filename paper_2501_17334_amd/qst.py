@@ -214,8 +214,9 @@ class Problem:
         logu=, accept=) torch device tensors [k, n_steps]; record: dict(every=,
         chains=, buf=) torch device tensor [chains, n_steps // every, D, D];
         surrogate: an Mlp.surrogate() (delayed acceptance); pairs: dict(every=,
-        chains=, x= bfloat16 [chains, n_steps // every, pair_width], ll= float64
-        [chains, n_steps // every])."""
+        chains=, x= bfloat16 [n_steps // every, chains, pair_width], ll= float64
+        [n_steps // every, chains]): the proposal of step (s + 1) * every of
+        chain c and its log L in row s * chains + c."""
         rd = self._run_desc(cfg, trace, record, stream, surrogate, pairs)
         arr = (C.c_void_p * 1)(self._h)
         st = _RunStats()
