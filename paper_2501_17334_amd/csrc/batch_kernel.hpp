@@ -42,17 +42,23 @@ constexpr size_t batch_lds_doubles()
            WgTables<Q>::kDoubles;
 }
 
+// One tile of qubit count Q.  Each qubit count is a callee of its own, with
+// the dynamic LDS declared here so that its accesses stay LDS instructions:
+// with all six chain steps inlined into one body the kernel needed long
+// branches and heavy register spilling, and its 5-qubit tiles computed wrong
+// likelihoods.
 template <int Q>
-__device__ __forceinline__ void batch_tile(const ChainArgs& A, int64_t chain0, double* lds)
+__device__ __attribute__((noinline)) void batch_tile(const ChainArgs& A, int64_t chain0)
 {
-    wg_tables_init<Q>(lds, threadIdx.x, kBatchWG);
+    extern __shared__ double batch_lds[];
+    wg_tables_init<Q>(batch_lds, threadIdx.x, kBatchWG);
     __syncthreads();
-    chain_tile<Q, BatchTeam<Q>::G, kBatchWG, kPathKron, kPrecF64>(A, chain0, lds, lds + WgTables<Q>::kDoubles);
+    chain_tile<Q, BatchTeam<Q>::G, kBatchWG, kPathKron, kPrecF64>(A, chain0, batch_lds,
+                                                                  batch_lds + WgTables<Q>::kDoubles);
 }
 
 __global__ __launch_bounds__(kBatchWG, 2) void k_chains_batch(BatchArgs B)
 {
-    extern __shared__ double lds[];
     __shared__ int32_t take;
     for (;;) {
         if (threadIdx.x == 0) take = atomicAdd(B.counter, 1);
@@ -63,12 +69,12 @@ __global__ __launch_bounds__(kBatchWG, 2) void k_chains_batch(BatchArgs B)
         const BatchItem I = B.items[it];
         const ChainArgs A = B.problems[I.problem];
         switch (I.q) {
-            case 1: batch_tile<1>(A, I.chain0, lds); break;
-            case 2: batch_tile<2>(A, I.chain0, lds); break;
-            case 3: batch_tile<3>(A, I.chain0, lds); break;
-            case 4: batch_tile<4>(A, I.chain0, lds); break;
-            case 5: batch_tile<5>(A, I.chain0, lds); break;
-            default: batch_tile<6>(A, I.chain0, lds); break;
+            case 1: batch_tile<1>(A, I.chain0); break;
+            case 2: batch_tile<2>(A, I.chain0); break;
+            case 3: batch_tile<3>(A, I.chain0); break;
+            case 4: batch_tile<4>(A, I.chain0); break;
+            case 5: batch_tile<5>(A, I.chain0); break;
+            default: batch_tile<6>(A, I.chain0); break;
         }
         __syncthreads();
     }

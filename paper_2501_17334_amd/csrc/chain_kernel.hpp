@@ -587,7 +587,7 @@ __device__ __forceinline__ double dense_loglik_wg(double* lds_teams, double* red
 // the chain tile
 // ---------------------------------------------------------------------------
 template <int Q, int G, int WG, int PATH, int PREC>
-__device__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tables, double* lds)
+__device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tables, double* lds)
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G, PATH>;
