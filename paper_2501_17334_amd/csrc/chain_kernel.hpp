@@ -360,6 +360,18 @@ __device__ __forceinline__ double xor_lane_stage(double v, int s)
     }
 }
 
+__device__ __forceinline__ float xor_lane_stage_f32(float v, int s)
+{
+    switch (s) {
+        case 0: return xor_lane_f32<1>(v);
+        case 1: return xor_lane_f32<2>(v);
+        case 2: return xor_lane_f32<4>(v);
+        case 3: return xor_lane_f32<8>(v);
+        case 4: return xor_lane_f32<16>(v);
+        default: return xor_lane_f32<32>(v);
+    }
+}
+
 template <int Q, int G>
 __device__ __forceinline__ void stage_pauli(const double* rhoP, double* pauli, int lane)
 {
@@ -389,6 +401,41 @@ __device__ __forceinline__ void stage_pauli(const double* rhoP, double* pauli, i
         const int r4 = __popc(m & zy) & 3;
         const double c = r4 == 0 ? re : (r4 == 1 ? -im : (r4 == 2 ? -re : im));
         // digit (m_q, zy_q): (0,0) -> I, (1,0) -> X, (1,1) -> Y, (0,1) -> Z
+        const int mu = (spread_bits(zy) << 1) | spread_bits(m ^ zy);
+        if (valid) pauli[mu] = c;
+    }
+}
+
+// The same Pauli coefficients with the transform in FP32 (the mixed-precision
+// Kronecker form): rho' is rounded to FP32 as it is read.
+template <int Q, int G>
+__device__ __forceinline__ void stage_pauli_f32(const double* rhoP, float* pauli, int lane)
+{
+    using Dm = Dims<Q>;
+    constexpr int D = Dm::D, D2 = Dm::D2;
+    constexpr int NPASS = (D2 + G - 1) / G;
+    const int a = lane & (D - 1);
+#pragma unroll 1
+    for (int e = 0; e < NPASS; ++e) {
+        const int item = lane + G * e;
+        const bool valid = (NPASS * G == D2) || item < D2;
+        const int m = valid ? (item >> Q) : 0;
+        const int b = a ^ m;
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        float re = static_cast<float>(rhoP[lo * D + hi]);
+        const float pim = static_cast<float>(rhoP[hi * D + lo]);
+        float im = (a == b) ? 0.0f : (a < b ? pim : -pim);
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const float ore = xor_lane_stage_f32(re, s);
+            const float oim = xor_lane_stage_f32(im, s);
+            const bool up = (a >> s) & 1;
+            re = up ? ore - re : re + ore;
+            im = up ? oim - im : im + oim;
+        }
+        const int zy = a;
+        const int r4 = __popc(m & zy) & 3;
+        const float c = r4 == 0 ? re : (r4 == 1 ? -im : (r4 == 2 ? -re : im));
         const int mu = (spread_bits(zy) << 1) | spread_bits(m ^ zy);
         if (valid) pauli[mu] = c;
     }
@@ -429,6 +476,38 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
         const double fr = log_parts(pos ? p : 1.0, tab, ex);
         part_e = __builtin_fma(n, static_cast<double>(ex), part_e);
         part_f = __builtin_fma(n, fr, part_f);
+    }
+}
+
+// The mixed-precision Kronecker form of stage_loglik: the transform and
+// log2 p (hardware logarithm) in FP32, the count-weighted sum of log2 p in
+// FP64.  A probability that rounds below the smallest normal FP32 value is
+// taken at that value.
+template <int Q, int G>
+__device__ __forceinline__ void stage_loglik_f32(const float* pauli, const double* __restrict__ nd,
+                                                 const double* tables, int lane, double& part)
+{
+    using Dm = Dims<Q>;
+    using S = TeamShape<Q, G>;
+    constexpr int D = Dm::D, KD = Dm::KD;
+    const uint16_t* mutab = reinterpret_cast<const uint16_t*>(tables + WgTables<Q>::kLogDoubles);
+    const int i = lane & (D - 1);
+#pragma unroll 1
+    for (int e = 0; e < S::NFL; ++e) {
+        const int f = lane + G * e;
+        const bool valid = (S::NFL * G == KD) || f < KD;
+        int mu;
+        if constexpr (WgTables<Q>::kMuTable) mu = valid ? mutab[f] : 0;
+        else mu = valid ? pauli_index<Q>(f / D, i) : 0;
+        float val = pauli[mu];
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const float other = xor_lane_stage_f32(val, s);
+            val = ((i >> s) & 1) ? other - val : val + other;
+        }
+        const float p = fmaxf(val * (1.0f / D), 0x1.0p-126f);
+        const double n = valid ? nd[f] : 0.0;
+        part = __builtin_fma(n, static_cast<double>(__builtin_amdgcn_logf(p)), part);
     }
 }
 
@@ -591,7 +670,8 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G, PATH>;
-    static_assert(PATH == kPathKron ? PREC == kPrecF64 : (G == 64 && WG == 1024), "unsupported path");
+    static_assert(PATH == kPathKron ? (PREC == kPrecF64 || PREC == kPrecF32) : (G == 64 && WG == 1024),
+                  "unsupported path");
     constexpr int D2 = Dm::D2, d = Dm::d, NB = Dm::NB;
     static_assert(WG % G == 0, "workgroup must hold whole teams");
 
@@ -650,6 +730,13 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         __syncthreads();
         if constexpr (PATH == kPathDense) {
             return dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, PATH>::kOffRed, A.mfrag, A.nd, logtab, tid);
+        } else if constexpr (PREC == kPrecF32) {
+            float* pauli32 = reinterpret_cast<float*>(pauli);
+            stage_pauli_f32<Q, G>(rhoP, pauli32, lane);
+            __syncthreads();
+            double part = 0.0;
+            stage_loglik_f32<Q, G>(pauli32, A.nd, tables, lane, part);
+            return kLn2 * team_sum<G>(part, misc + 4, lane);
         } else {
             stage_pauli<Q, G>(rhoP, pauli, lane);
             __syncthreads();
@@ -830,7 +917,7 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainA
 
 // Eq. (likelihood) for n given density matrices (complex, interleaved,
 // row-major), one team per matrix.
-template <int Q, int G, int WG>
+template <int Q, int G, int WG, int PREC = kPrecF64>
 __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, const double* rho,
                                                int64_t n, double* ll_out)
 {
@@ -855,15 +942,25 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
         rhoP[p] = a <= b ? rho[(c * D2 + a * D + b) * 2] : rho[(c * D2 + b * D + a) * 2 + 1];
     }
     __syncthreads();
-    stage_pauli<Q, G>(rhoP, pauli, lane);
-    __syncthreads();
-    double part_e = 0.0, part_f = 0.0;
-    int bad = 0;
-    stage_loglik<Q, G>(pauli, nd, tables, lane, part_e, part_f, bad);
-    const double tot_e = team_sum<G>(part_e, misc + 4, lane);
-    const double tot_f = team_sum<G>(part_f, misc + 4, lane);
-    const int anybad = team_or<G>(bad, misc + 4, lane);
-    if (live && lane == 0) ll_out[idx] = anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
+    if constexpr (PREC == kPrecF32) {
+        float* pauli32 = reinterpret_cast<float*>(pauli);
+        stage_pauli_f32<Q, G>(rhoP, pauli32, lane);
+        __syncthreads();
+        double part = 0.0;
+        stage_loglik_f32<Q, G>(pauli32, nd, tables, lane, part);
+        const double tot = team_sum<G>(part, misc + 4, lane);
+        if (live && lane == 0) ll_out[idx] = kLn2 * tot;
+    } else {
+        stage_pauli<Q, G>(rhoP, pauli, lane);
+        __syncthreads();
+        double part_e = 0.0, part_f = 0.0;
+        int bad = 0;
+        stage_loglik<Q, G>(pauli, nd, tables, lane, part_e, part_f, bad);
+        const double tot_e = team_sum<G>(part_e, misc + 4, lane);
+        const double tot_f = team_sum<G>(part_f, misc + 4, lane);
+        const int anybad = team_or<G>(bad, misc + 4, lane);
+        if (live && lane == 0) ll_out[idx] = anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
+    }
 }
 
 // Dense-path Eq. (likelihood) for n given density matrices: 16 matrices per

@@ -148,4 +148,27 @@ __device__ __forceinline__ double xor_lane(double v)
     }
 }
 
+// FP32 forms of the same lane exchanges (one 32-bit DPP move per step).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int MASK>
+__device__ __forceinline__ float xor_lane_f32(float v)
+{
+    if constexpr (MASK == 1) {
+        return dpp_f32<kDppQuadXor1>(v);
+    } else if constexpr (MASK == 2) {
+        return dpp_f32<kDppQuadXor2>(v);
+    } else if constexpr (MASK == 4) {
+        return dpp_f32<kDppRowHalfMirror>(dpp_f32<kDppQuadXor3>(v));
+    } else if constexpr (MASK == 8) {
+        return dpp_f32<kDppRowHalfMirror>(dpp_f32<kDppRowMirror>(v));
+    } else {
+        return __shfl_xor(v, MASK, 64);
+    }
+}
+
 }  // namespace qst

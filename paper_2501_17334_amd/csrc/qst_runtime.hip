@@ -233,7 +233,7 @@ void launch_loglik_dense_t(const double* nd, const void* mfrag, const double* rh
     hip_check(hipGetLastError(), "dense loglik kernel launch");
 }
 
-template <int Q, int G, int WG>
+template <int Q, int G, int WG, int PREC>
 void launch_loglik_t(const double* nd, const double* rho, int64_t n, double* out, hipStream_t s)
 {
     using S = qst::TeamShape<Q, G>;
@@ -242,12 +242,13 @@ void launch_loglik_t(const double* nd, const double* rho, int64_t n, double* out
     const size_t lds = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q>::kDoubles) * sizeof(double);
     static bool attr_done = false;
     if (!attr_done) {
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_loglik<Q, G, WG>),
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_loglik<Q, G, WG, PREC>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)),
                   "hipFuncSetAttribute");
         attr_done = true;
     }
-    hipLaunchKernelGGL((qst::k_loglik<Q, G, WG>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s, nd,
+    if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many states for one launch");
+    hipLaunchKernelGGL((qst::k_loglik<Q, G, WG, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s, nd,
                        rho, n, out);
     hip_check(hipGetLastError(), "loglik kernel launch");
 }
@@ -265,8 +266,10 @@ void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a,
 #undef QST_DENSE
         fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
     }
-#define QST_CASE(q, g, wg) \
-    if (Q == q && sh.G == g && sh.WG == wg) return launch_chains_t<q, g, wg, kPathKron, kPrecF64>(a, s);
+#define QST_CASE(q, g, wg)                                                                              \
+    if (Q == q && sh.G == g && sh.WG == wg)                                                             \
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32>(a, s)                  \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64>(a, s);
     QST_CASE(1, 8, 64) QST_CASE(1, 16, 64) QST_CASE(1, 64, 64)
     QST_CASE(2, 16, 64) QST_CASE(2, 32, 64) QST_CASE(2, 64, 64)
     QST_CASE(3, 32, 64) QST_CASE(3, 64, 64)
@@ -291,17 +294,24 @@ void launch_loglik_dense(int Q, int prec, const double* nd, const void* mfrag, c
     fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
 }
 
-void launch_loglik(int Q, const double* nd, const double* rho, int64_t n, double* out, hipStream_t s)
+template <int PREC>
+void launch_loglik_p(int Q, const double* nd, const double* rho, int64_t n, double* out, hipStream_t s)
 {
     switch (Q) {
-        case 1: return launch_loglik_t<1, 8, 64>(nd, rho, n, out, s);
-        case 2: return launch_loglik_t<2, 16, 64>(nd, rho, n, out, s);
-        case 3: return launch_loglik_t<3, 32, 64>(nd, rho, n, out, s);
-        case 4: return launch_loglik_t<4, 64, 64>(nd, rho, n, out, s);
-        case 5: return launch_loglik_t<5, 64, 64>(nd, rho, n, out, s);
-        case 6: return launch_loglik_t<6, 256, 256>(nd, rho, n, out, s);
+        case 1: return launch_loglik_t<1, 8, 64, PREC>(nd, rho, n, out, s);
+        case 2: return launch_loglik_t<2, 16, 64, PREC>(nd, rho, n, out, s);
+        case 3: return launch_loglik_t<3, 32, 64, PREC>(nd, rho, n, out, s);
+        case 4: return launch_loglik_t<4, 64, 64, PREC>(nd, rho, n, out, s);
+        case 5: return launch_loglik_t<5, 64, 64, PREC>(nd, rho, n, out, s);
+        case 6: return launch_loglik_t<6, 256, 256, PREC>(nd, rho, n, out, s);
     }
     fail(QST_ERR_INVALID, "bad Q");
+}
+
+void launch_loglik(int Q, int prec, const double* nd, const double* rho, int64_t n, double* out, hipStream_t s)
+{
+    if (prec == qst::kPrecF32) return launch_loglik_p<qst::kPrecF32>(Q, nd, rho, n, out, s);
+    return launch_loglik_p<qst::kPrecF64>(Q, nd, rho, n, out, s);
 }
 
 struct DeviceGuard {
@@ -442,7 +452,8 @@ void validate_run(const qst_problem* p, const qst_run_desc& r)
     }
     if (r.surrogate) {
         if (!r.surrogate->model) fail(QST_ERR_INVALID, "surrogate has no model (use qst_mlp_surrogate)");
-        if (p->path != QST_PATH_KRON) fail(QST_ERR_UNSUPPORTED, "delayed acceptance uses the FP64 Kronecker path");
+        if (p->path != QST_PATH_KRON || p->precision != QST_FP64)
+            fail(QST_ERR_UNSUPPORTED, "delayed acceptance uses the FP64 Kronecker path");
     }
 }
 
@@ -478,10 +489,10 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
         p->KD = p->K * p->D;
         p->device = desc->device;
         p->precision = desc->precision;
-        p->path = desc->path == QST_PATH_AUTO ? (desc->precision == QST_FP64 ? QST_PATH_KRON : QST_PATH_DENSE)
+        p->path = desc->path == QST_PATH_AUTO ? (desc->precision == QST_BF16X3 ? QST_PATH_DENSE : QST_PATH_KRON)
                                               : desc->path;
-        if (p->path == QST_PATH_KRON && p->precision != QST_FP64)
-            fail(QST_ERR_UNSUPPORTED, "the Kronecker path is FP64 only; reduced precision needs QST_PATH_DENSE");
+        if (p->path == QST_PATH_KRON && p->precision == QST_BF16X3)
+            fail(QST_ERR_UNSUPPORTED, "the Kronecker path runs in FP64 or FP32; BF16x3 needs QST_PATH_DENSE");
         if (p->path == QST_PATH_DENSE && Q > 4)
             fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
         p->counts.assign(desc->counts, desc->counts + p->KD);
@@ -635,7 +646,8 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
     size_t lds = 0;
     for (int i = 0; i < n; ++i) {
         qst_problem* p = problems[i];
-        if (p->path != QST_PATH_KRON) fail(QST_ERR_UNSUPPORTED, "batched launches use the FP64 Kronecker path");
+        if (p->path != QST_PATH_KRON || p->precision != QST_FP64)
+            fail(QST_ERR_UNSUPPORTED, "batched launches use the FP64 Kronecker path");
         args[i] = make_args(p, runs[i]);
         const int per = qst::kBatchWG / batch_team(p->Q);
         for (int64_t c0 = 0; c0 < p->R; c0 += per) {
@@ -856,14 +868,15 @@ qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double
         const qst_path pth = path == QST_PATH_AUTO ? p->path : path;
         if (precision != QST_FP64 && precision != QST_FP32 && precision != QST_BF16X3)
             fail(QST_ERR_INVALID, "unknown precision");
-        if (pth == QST_PATH_KRON && precision != QST_FP64)
-            fail(QST_ERR_UNSUPPORTED, "the Kronecker path is FP64 only");
+        if (pth == QST_PATH_KRON && precision == QST_BF16X3)
+            fail(QST_ERR_UNSUPPORTED, "the Kronecker path runs in FP64 or FP32");
         DeviceGuard g(p->device);
         if (pth == QST_PATH_DENSE) {
             const void* f = const_cast<qst_problem*>(p)->fragments(precision);
             launch_loglik_dense(p->Q, precision, p->nd, f, rho, n, ll_out, static_cast<hipStream_t>(stream));
         } else {
-            launch_loglik(p->Q, p->nd, rho, n, ll_out, static_cast<hipStream_t>(stream));
+            launch_loglik(p->Q, precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64, p->nd, rho, n, ll_out,
+                          static_cast<hipStream_t>(stream));
         }
     });
 }

@@ -368,10 +368,13 @@ def list_launch_shapes(n_qubits):
     return list(zip(T, W))
 
 
-def run_batch(problems, configs, stats=True, stream=None):
-    """qst_run_chains on several problems in one launch (the uneven batch)."""
+def run_batch(problems, configs, stats=True, stream=None, traces=None):
+    """qst_run_chains on several problems in one launch (the uneven batch).
+    traces: optional list (one entry per problem, None or a trace dict as in
+    Problem.run)."""
     n = len(problems)
-    rds = (_RunDesc * n)(*[p._run_desc(c, None, None, stream) for p, c in zip(problems, configs)])
+    traces = traces or [None] * n
+    rds = (_RunDesc * n)(*[p._run_desc(c, t, None, stream) for p, c, t in zip(problems, configs, traces)])
     hs = (C.c_void_p * n)(*[p._h for p in problems])
     st = (_RunStats * n)()
     _check(lib().qst_run_chains(hs, n, rds, st if stats else None))

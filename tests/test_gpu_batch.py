@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import oracle as O
 from paper_2501_17334_amd import qst, synth
 
 pytestmark = pytest.mark.gpu
@@ -54,6 +55,36 @@ def test_batch_equals_solo():
     finally:
         for q, sh in saved.items():
             qst.set_launch_shape(q, *sh)
+
+
+def test_batch_matches_oracle():
+    """Every problem of a 1..6-qubit batch against the oracle: per-step log L
+    of the proposals to 1e-10 relative while the decisions agree."""
+    probs = _problems()
+    chains = {1: 6, 2: 5, 3: 4, 4: 3, 5: 3, 6: 2}
+    steps = {1: 60, 2: 40, 3: 20, 4: 10, 5: 5, 6: 2}
+    cfgs = [qst.RunConfig(n_chains=chains[p.n_qubits], n_steps=steps[p.n_qubits], seed=p.seed, beta0=0.05,
+                          adapt_every=0) for p in probs]
+    traces = [dict(chains=c.n_chains,
+                   llprop=torch.full((c.n_chains, c.n_steps), float("nan"), dtype=torch.float64, device="cuda"),
+                   logu=torch.zeros((c.n_chains, c.n_steps), dtype=torch.float64, device="cuda"),
+                   accept=torch.zeros((c.n_chains, c.n_steps), dtype=torch.int8, device="cuda")) for c in cfgs]
+    batch = [qst.Problem(p.n_qubits, p.counts) for p in probs]
+    print("[batch oracle] run", flush=True)
+    qst.run_batch(batch, cfgs, traces=traces)
+    torch.cuda.synchronize()
+    for p, c, tr in zip(probs, cfgs, traces):
+        ch = O.Chains(p.n_qubits, p.counts, O.RunParams(n_chains=c.n_chains, n_steps=0, seed=p.seed, beta0=0.05,
+                                                         adapt_every=0, trace_chains=c.n_chains))
+        o = ch.run(c.n_steps)
+        g_ll = tr["llprop"].cpu().numpy()
+        g_acc = tr["accept"].cpu().numpy()
+        for r in range(c.n_chains):
+            same = g_acc[r] == o["trace_accept"][r]
+            k = c.n_steps if same.all() else int(np.argmin(same)) + 1
+            a, b = o["trace_llprop"][r, :k], g_ll[r, :k]
+            assert np.all(np.abs(a - b) <= 1e-10 * np.abs(a)), (p.n_qubits, r)
+        print(f"[batch oracle] Q={p.n_qubits} ok", flush=True)
 
 
 def test_batch_resume_and_stats():
