@@ -96,6 +96,166 @@ def dense_gemm_rates(qst, synth, torch, prob, n_states=65536, reps=5):
     return res
 
 
+def chosen_forms(qst, torch, np, prob, cfg, record, plain_pool, plain_ms, plain_tau, plain_ess_between,
+                 dense_steps=1000):
+    """The production forms on the same workload, same seeds and the pilot
+    beta: the mixed-precision Kronecker form over the full run (rate, ESS
+    from its own records, pooled-mean difference against the plain FP64 run
+    in units of the plain run's between-chain standard error), and the dense
+    MFMA contraction inside the chain kernel in each precision over a short
+    run (rate only)."""
+    import dataclasses
+    out = {}
+    Q, R, NT = prob.n_qubits, cfg.n_chains, cfg.n_steps
+    se_f = float(np.sqrt(np.sum(plain_pool["se_re"] ** 2 + plain_pool["se_im"] ** 2)))
+
+    def timed(P, c, rec):
+        P.run(dataclasses.replace(c, n_chains=256, n_steps=10), stats=False)     # module load, attributes
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        P.run(c, record=rec, stats=False)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    P = qst.Problem(Q, prob.counts, precision="fp32", path="kron")
+    rec_buf = record["buf"]
+    ms = timed(P, cfg, record)
+    pool = P.pool()
+    every = record["every"]
+    first = (cfg.burn_in + every - 1) // every
+    n_rec = NT // every - first
+    c = qst.acf(rec_buf[:, first:].contiguous(), l_max=min(200, n_rec - 1))
+    tau = qst.iact(c)
+    var = np.concatenate([(pool["second_re"] - pool["mean"].real ** 2).ravel(),
+                          (pool["second_im"] - pool["mean"].imag ** 2).ravel()])
+    se2 = np.concatenate([pool["se_re"].ravel() ** 2, pool["se_im"].ravel() ** 2])
+    ess_between = float(np.sum(var) / np.sum(se2))
+    diff = float(np.sqrt(np.sum(np.abs(pool["mean"] - plain_pool["mean"]) ** 2)))
+    out["kron_fp32"] = {
+        "what": "Pauli coefficients, per-setting Walsh-Hadamard transforms and log2 p in FP32, "
+                "count-weighted sum and acceptance in FP64; full run, same seeds and beta",
+        "chain_steps_per_s": R * NT / (ms / 1e3), "ms": ms,
+        "speedup_vs_plain_fp64": plain_ms / ms,
+        "tau": tau, "tau_plain_fp64": plain_tau,
+        "ess_per_s": n_rec * R / tau / (ms / 1e3),
+        "between_chain_ess_per_s": ess_between / (ms / 1e3),
+        "between_chain_ess_per_s_plain_fp64": plain_ess_between / (plain_ms / 1e3),
+        "mean_diff_frobenius_vs_plain_fp64": diff, "plain_fp64_se_frobenius": se_f,
+        "mean_diff_in_se": diff / se_f,
+    }
+    P.close()
+    if Q <= 4:
+        for prec in ("fp64", "fp32", "bf16x3"):
+            P = qst.Problem(Q, prob.counts, precision=prec, path="dense")
+            c2 = dataclasses.replace(cfg, n_steps=dense_steps, burn_in=0)
+            ms = timed(P, c2, None)
+            out[f"dense_{prec}"] = {"what": f"dense MFMA contraction in the chain kernel ({prec}), "
+                                            f"{dense_steps}-step run, rate only",
+                                    "chain_steps_per_s": R * dense_steps / (ms / 1e3), "ms": ms}
+            P.close()
+    return out
+
+
+def delayed_acceptance(qst, surrogate, synth, torch, np, name="c4", warm=4000, pair_steps=2000, pair_every=20,
+                       iters=4000, steps=1000, skill_chains=64, skill_steps=300):
+    """Delayed acceptance with the learned surrogate on its own workload (the
+    5-qubit problem, 16384 chains): pilot beta, warm-up, training pairs from
+    the chains, training on the GPU, then the same resumed state run plain
+    and with the surrogate.  Also the surrogate's skill where the first stage
+    needs it: predicted against exact log-likelihood differences of
+    consecutive pCN proposals."""
+    prob = synth.make_problem(name)
+    Q, R = prob.n_qubits, prob.n_chains
+
+    def start():
+        P = qst.Problem(Q, prob.counts)
+        P.run(qst.RunConfig(n_chains=256, n_steps=4000, seed=prob.seed + 99, beta0=0.1, adapt_every=100),
+              stats=False)
+        beta = float(np.median(P.state()[2]))
+        P.run(qst.RunConfig(n_chains=R, n_steps=warm, seed=prob.seed, beta0=beta, adapt_every=500), stats=False)
+        return P, beta
+
+    A, beta = start()
+    pcfg = qst.RunConfig(n_chains=R, n_steps=pair_steps, seed=prob.seed, beta0=beta, adapt_every=500, resume=True)
+    pairs = surrogate.collect_pairs(A, pcfg, pair_every=pair_every)
+    net = qst.Mlp(A.pair_width, 512, 512)
+    net.set_params(surrogate.init_params(A.pair_width, 512, 512, seed=1))
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    tr = surrogate.train(net, pairs, iters, batch=1024, lr=1e-3, lr_final=5e-5)
+    b.record()
+    torch.cuda.synchronize()
+    train_ms = a.elapsed_time(b)
+    n_pairs = int(pairs.x.shape[0])
+    del pairs
+    torch.cuda.empty_cache()
+    B, _ = start()
+    B.run(pcfg, stats=False)
+    cfg = qst.RunConfig(n_chains=R, n_steps=steps, seed=prob.seed, beta0=beta, adapt_every=500, resume=True)
+
+    def timed(P, **kw):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        st = P.run(cfg, stats=True, **kw)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b), st
+
+    ms_plain, st_plain = timed(B)
+    ms_da, st_da = timed(A, surrogate=net.surrogate())
+    # skill on consecutive proposals of the plain chains
+    C, T = skill_chains, skill_steps
+    x = torch.empty((T * C, B.pair_width), dtype=torch.bfloat16, device="cuda")
+    ll = torch.empty(T * C, dtype=torch.float64, device="cuda")
+    trc = dict(chains=C, llprop=torch.zeros((C, T), dtype=torch.float64, device="cuda"),
+               logu=torch.zeros((C, T), dtype=torch.float64, device="cuda"),
+               accept=torch.zeros((C, T), dtype=torch.int8, device="cuda"))
+    x0, l0, _, _ = B.state()
+    B.run(qst.RunConfig(n_chains=R, n_steps=T, seed=prob.seed + 1, beta0=beta, adapt_every=500, resume=True),
+          trace=trc, pairs=dict(every=1, chains=C, x=x, ll=ll), stats=False)
+    s_prop = net.predict(x).double().cpu().numpy().reshape(T, C)
+    l_prop = ll.cpu().numpy().reshape(T, C)
+    acc = trc["accept"].cpu().numpy()
+    xs0 = torch.from_numpy(np.pad(x0[:C], ((0, 0), (0, B.pair_width - B.d)))).cuda()
+    s_cur = net.predict(xs0).double().cpu().numpy()
+    l_cur = l0[:C].copy()
+    dS, dL = [], []
+    for t in range(T):
+        dS.append(s_prop[t] - s_cur)
+        dL.append(l_prop[t] - l_cur)
+        s_cur = np.where(acc[:, t] == 1, s_prop[t], s_cur)
+        l_cur = np.where(acc[:, t] == 1, l_prop[t], l_cur)
+    dS, dL = np.concatenate(dS), np.concatenate(dL)
+    ok = np.isfinite(dL)
+    dS, dL = dS[ok], dL[ok]
+    rate_plain = R * steps / (ms_plain / 1e3)
+    rate_da = R * steps / (ms_da / 1e3)
+    acc_plain = st_plain["accepted"] / st_plain["proposed"]
+    acc_da = st_da["accepted"] / st_da["proposed"]
+    A.close()
+    B.close()
+    net.close()
+    return {
+        "workload": f"{name}: {Q}-qubit, {R} chains; pilot beta {beta:.4g}; warm-up {warm} steps; "
+                    f"{n_pairs} training pairs (every {pair_every} steps over {pair_steps}); then {steps} steps "
+                    f"plain and delayed from the same state",
+        "network": f"{B.pair_width}->512->512->1 GELU, BF16 products, FP32 accumulation, Adam {iters} iterations",
+        "train_ms": train_ms, "val_mse_standardised": tr.val_loss, "target_sd": tr.sd,
+        "plain": {"chain_steps_per_s": rate_plain, "accept": acc_plain},
+        "delayed": {"chain_steps_per_s": rate_da, "accept": acc_da,
+                    "stage1_pass": st_da["stage1_passed"] / st_da["proposed"]},
+        "skill": {"corr_dsurrogate_dloglik": float(np.corrcoef(dS, dL)[0, 1]),
+                  "rms_dloglik": float(np.sqrt(np.mean(dL ** 2))),
+                  "rms_error": float(np.sqrt(np.mean((dS - dL) ** 2)))},
+        # accepted moves per second: the chains are the same method, so this is
+        # the ratio of their sampling efficiency at equal step size
+        "gain_accepted_moves_per_s": (rate_da * acc_da) / (rate_plain * acc_plain),
+        "gain_chain_steps_per_s": rate_da / rate_plain,
+    }
+
+
 def pilot_beta(qst, P, seed, n_chains=256, n_steps=6000):
     """Algorithm 2's own adaptation (every 100 steps here) run on a pilot set
     of chains; the median final beta starts the measured run."""
@@ -140,6 +300,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense-gemm", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-delayed", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -251,6 +413,13 @@ def main():
                      "kernel": f"k_chains<Q={Q}>", "kernel_ms": ms_kernel,
                      "flop_per_chain_step": flop, "kernel_source_hash": khash},
     }
+    if not args.no_forms:
+        print("[bench] chosen forms", file=sys.stderr, flush=True)
+        out["forms"] = chosen_forms(qst, torch, np, prob, cfg, record, pool, ms_step, tau, ess_between)
+        if not args.no_delayed:
+            from paper_2501_17334_amd import surrogate
+            print("[bench] delayed acceptance (5-qubit workload)", file=sys.stderr, flush=True)
+            out["forms"]["delayed_acceptance"] = delayed_acceptance(qst, surrogate, synth, torch, np)
     if args.config == "c3" and not args.no_dense_gemm:
         out["dense_gemm"] = dense_gemm_rates(qst, synth, torch, prob)
     if not args.no_cpu_baseline:
