@@ -126,3 +126,51 @@ def test_training_on_chain_pairs():
     pred = net.predict(xs).cpu().numpy().astype(np.float64)
     truth = pairs.ll[:256].cpu().numpy()
     assert np.sqrt(np.mean((pred - truth) ** 2)) < np.sqrt(0.85 * 1.3) * res.sd
+
+
+def test_what_the_trained_network_gains():
+    """Delayed acceptance with the trained network against the same chains
+    without it, from the same state and the same streams: the counts that
+    decide the gain (stage-1 pass rate = exact evaluations per step,
+    acceptance, accepted moves per exact evaluation) are measured and
+    printed; the stage counts must be consistent and the posterior mean of
+    the delayed run must agree with the plain run within the Monte Carlo
+    error (the second stage keeps the target exact whatever the network)."""
+    Q = 2
+    prob = synth.make_problem("c2")
+    R, T = 2048, 1500
+
+    def start():
+        P = qst.Problem(Q, prob.counts)
+        P.run(qst.RunConfig(n_chains=R, n_steps=3000, seed=21, beta0=0.1, adapt_every=100), stats=False)
+        return P
+
+    A = start()
+    beta = float(np.median(A.state()[2]))
+    pcfg = qst.RunConfig(n_chains=R, n_steps=400, seed=21, beta0=beta, adapt_every=0, resume=True)
+    pairs = surrogate.collect_pairs(A, pcfg, pair_every=4)
+    net = qst.Mlp(A.pair_width, 128, 128)
+    net.set_params(surrogate.init_params(A.pair_width, 128, 128, seed=2))
+    res = surrogate.train(net, pairs, iters=2000, batch=1024, lr=1e-3, lr_final=1e-4)
+    B = start()
+    B.run(pcfg, stats=False)
+    assert np.array_equal(A.state()[0], B.state()[0])
+    cfg = qst.RunConfig(n_chains=R, n_steps=T, seed=22, beta0=beta, adapt_every=0, resume=True, burn_in=0)
+    st_p = B.run(cfg)
+    st_d = A.run(cfg, surrogate=net.surrogate())
+    torch.cuda.synchronize()
+    assert st_p["proposed"] == st_d["proposed"] == R * T
+    assert st_d["accepted"] <= st_d["stage1_passed"] <= st_d["proposed"]
+    acc_p = st_p["accepted"] / st_p["proposed"]
+    acc_d = st_d["accepted"] / st_d["proposed"]
+    pass1 = st_d["stage1_passed"] / st_d["proposed"]
+    out = {"val_mse_standardised": res.val_loss, "plain_accept": acc_p, "delayed_accept": acc_d,
+           "stage1_pass": pass1, "exact_evaluations_saved": 1.0 - pass1,
+           "accepted_per_exact_evaluation_plain": acc_p,
+           "accepted_per_exact_evaluation_delayed": st_d["accepted"] / max(st_d["stage1_passed"], 1)}
+    print(f"[gain] {out}", flush=True)
+    pa, pb = A.pool(), B.pool()
+    for part, se in (("real", "se_re"), ("imag", "se_im")):
+        diff = np.abs(getattr(pa["mean"], part) - getattr(pb["mean"], part))
+        tol = 5 * np.sqrt(pa[se] ** 2 + pb[se] ** 2) + 1e-12
+        assert np.all(diff <= tol), (part, diff, tol)
