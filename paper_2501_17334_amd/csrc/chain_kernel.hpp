@@ -279,22 +279,41 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
         // rho = Zs Zs^dag with Zs = Z diag(sqrt w): Re rho = Zr Zr^T + Zi Zi^T and
         // Im rho = Zi Zr^T - Zr Zi^T, i.e. two 16x16 real products with K = 32,
         // eight v_mfma_f64_16x16x4f64 each.  Operand lane l carries
-        // A[l % 16][k0 + l / 16]; for a Gram product the B operand is the same value.
-        stage_weights<Q, G, true>(ybuf, wt, lane);
-        __syncthreads();
-        typedef double double4_t __attribute__((ext_vector_type(4)));
-        double4_t re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+        // A[l % 16][k0 + l / 16]; for a Gram product the B operand is the same
+        // value.  The lane already holds z_ij for its four columns j, so the
+        // column norms |z_j|^2 are butterfly sums over the 16 lanes of its row
+        // group and the weights never pass through LDS.
         const int i = lane & 15, kq = lane >> 4;
+        double V = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < D; ++j) {
+            const double v = ybuf[2 * D2 + j];
+            V += v * v;
+        }
+        double zr[4], zi[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int j = 4 * t + kq;
-            const double sj = wt[j];
-            const double zr = ybuf[j * D + i] * sj;
-            const double zi = ybuf[D2 + j * D + i] * sj;
-            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zr, zr, re, 0, 0, 0);
-            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zi, zi, re, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f64_16x16x4f64(zi, zr, im, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f64_16x16x4f64(-zr, zi, im, 0, 0, 0);
+            zr[t] = ybuf[j * D + i];
+            zi[t] = ybuf[D2 + j * D + i];
+            double nz = zr[t] * zr[t] + zi[t] * zi[t];
+            nz += xor_lane<1>(nz);
+            nz += xor_lane<2>(nz);
+            nz += xor_lane<4>(nz);
+            nz += xor_lane<8>(nz);
+            const double v = ybuf[2 * D2 + j];
+            const double sj = sqrt((v * v / V) / nz);
+            zr[t] *= sj;
+            zi[t] *= sj;
+        }
+        typedef double double4_t __attribute__((ext_vector_type(4)));
+        double4_t re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zr[t], zr[t], re, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zi[t], re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zr[t], im, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f64_16x16x4f64(-zr[t], zi[t], im, 0, 0, 0);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {

@@ -29,6 +29,21 @@ struct Block4 {
     uint64_t w[4];
 };
 
+// Full 64 x 64 -> 128-bit product from four 32 x 32 + 64 multiply-adds
+// (v_mad_u64_u32): with a = a1:a0 and b = b1:b0, t = a0 b1 + hi(a0 b0) and
+// u = a1 b0 + lo(t) cannot overflow 64 bits, and
+// a b = lo(a0 b0) + 2^32 lo(u) + 2^64 (a1 b1 + hi(t) + hi(u)).
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi)
+{
+    const uint64_t a0 = static_cast<uint32_t>(a), a1 = a >> 32;
+    const uint64_t b0 = static_cast<uint32_t>(b), b1 = b >> 32;
+    const uint64_t p00 = a0 * b0;
+    const uint64_t t = a0 * b1 + (p00 >> 32);
+    const uint64_t u = a1 * b0 + static_cast<uint32_t>(t);
+    hi = a1 * b1 + ((t >> 32) + (u >> 32));
+    lo = (u << 32) | static_cast<uint32_t>(p00);
+}
+
 __device__ __forceinline__ Block4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                                  uint64_t k0, uint64_t k1)
 {
@@ -38,10 +53,9 @@ __device__ __forceinline__ Block4 philox4x64_10(uint64_t c0, uint64_t c1, uint64
             k0 += kPhiloxW0;
             k1 += kPhiloxW1;
         }
-        const uint64_t lo0 = kPhiloxM0 * c0;
-        const uint64_t hi0 = __umul64hi(kPhiloxM0, c0);
-        const uint64_t lo1 = kPhiloxM1 * c2;
-        const uint64_t hi1 = __umul64hi(kPhiloxM1, c2);
+        uint64_t lo0, hi0, lo1, hi1;
+        mulhilo64(kPhiloxM0, c0, lo0, hi0);
+        mulhilo64(kPhiloxM1, c2, lo1, hi1);
         const uint64_t n0 = hi1 ^ c1 ^ k0;
         const uint64_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
