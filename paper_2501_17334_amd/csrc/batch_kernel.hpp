@@ -32,7 +32,7 @@ struct BatchArgs {
 // Team size of each qubit count inside a batch launch.
 template <int Q>
 struct BatchTeam {
-    static constexpr int G = Q == 1 ? 8 : Q == 2 ? 16 : Q == 3 ? 32 : Q == 4 ? 64 : 512;
+    static constexpr int G = Q == 1 ? 8 : Q == 2 ? 16 : Q == 3 ? 32 : Q == 4 ? 64 : Q == 5 ? 256 : 512;
 };
 
 template <int Q>

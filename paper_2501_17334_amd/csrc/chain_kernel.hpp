@@ -225,18 +225,35 @@ __device__ __forceinline__ int team_or(int v, double* scratch, int lane)
 // ---------------------------------------------------------------------------
 
 // The packed-rho entries a lane owns: p = lane + G e, except on the MFMA
-// path (D = 16, one wavefront per chain), where a lane owns the four entries
-// of the 16x16x4 FP64 MFMA result layout: row lane / 16 + 4 e, column lane % 16.
+// path, where rho is formed by 16x16x4 FP64 MFMAs tile by tile: the D x D
+// result is (D/16)^2 tiles of 16 x 16, the team's wavefronts take equal
+// shares of them, and a lane owns, per tile, the four entries of the MFMA
+// result layout (row lane % 64 / 16 + 4 r, column lane % 16 of the tile).
+// Used for one-wave 4-qubit teams and for 5- and 6-qubit teams whose
+// wavefront count divides the tile count.
 template <int Q, int G>
 struct RhoLayout {
-    static constexpr bool kMfma = (Q == 4 && G == 64);
+    static constexpr int kTileDim = Q >= 4 ? (1 << (Q - 4)) : 0;   // tiles per row of rho
+    static constexpr int kTiles = kTileDim * kTileDim;
+    static constexpr int kWaves = G >= 64 ? G / 64 : 0;
+    static constexpr bool kMfma =
+        (Q == 4 && G == 64) || (Q >= 5 && kWaves > 0 && kTiles % (kWaves > 0 ? kWaves : 1) == 0);
+    static constexpr int kTilesPerWave = kMfma ? kTiles / kWaves : 0;
 };
 
 template <int Q, int G>
 __device__ __forceinline__ int packed_slot(int lane, int e)
 {
-    if constexpr (RhoLayout<Q, G>::kMfma) return ((lane >> 4) + 4 * e) * 16 + (lane & 15);
-    else return lane + G * e;
+    using L = RhoLayout<Q, G>;
+    if constexpr (L::kMfma) {
+        constexpr int D = 1 << Q;
+        const int tile = (lane >> 6) * L::kTilesPerWave + (e >> 2);
+        const int rb = tile / L::kTileDim, cb = tile % L::kTileDim;
+        const int l = lane & 63;
+        return (16 * rb + (l >> 4) + 4 * (e & 3)) * D + 16 * cb + (l & 15);
+    } else {
+        return lane + G * e;
+    }
 }
 
 // Column weights w_j = (v_j^2 / sum_k v_k^2) / |z_j|^2 from the parameters in
@@ -275,7 +292,68 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
     constexpr int D = Dm::D, D2 = Dm::D2;
-    if constexpr (RhoLayout<Q, G>::kMfma) {
+    if constexpr (RhoLayout<Q, G>::kMfma && Q >= 5) {
+        // The same Gram products tile by tile.  Column weights first: G / D
+        // lanes share a column, sum |z_ij|^2 over their rows and combine by
+        // butterflies; sqrt(w_j) goes to LDS for the operand loads.
+        using L = RhoLayout<Q, G>;
+        constexpr int LPC = G / D;          // lanes per column: 2, 4 or 8
+        constexpr int RPL = D / LPC;        // rows per lane
+        static_assert(LPC >= 2 && LPC <= 8, "column groups must sit inside a DPP row");
+        double V = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < D; ++j) {
+            const double v = ybuf[2 * D2 + j];
+            V += v * v;
+        }
+        {
+            const int j = lane / LPC, q = lane % LPC;
+            double nz = 0.0;
+#pragma unroll 4
+            for (int r = 0; r < RPL; ++r) {
+                const int i = q * RPL + r;
+                const double re = ybuf[j * D + i];
+                const double im = ybuf[D2 + j * D + i];
+                nz += re * re + im * im;
+            }
+            nz += xor_lane<1>(nz);
+            if constexpr (LPC >= 4) nz += xor_lane<2>(nz);
+            if constexpr (LPC >= 8) nz += xor_lane<4>(nz);
+            if (q == 0) {
+                const double v = ybuf[2 * D2 + j];
+                wt[j] = sqrt((v * v / V) / nz);
+            }
+        }
+        __syncthreads();
+        typedef double double4_t __attribute__((ext_vector_type(4)));
+        const int l = lane & 63, i = l & 15, kq = l >> 4;
+#pragma unroll
+        for (int m = 0; m < L::kTilesPerWave; ++m) {
+            const int tile = (lane >> 6) * L::kTilesPerWave + m;
+            const int r0 = 16 * (tile / L::kTileDim), c0 = 16 * (tile % L::kTileDim);
+            double4_t re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int s = 0; s < D / 4; ++s) {
+                const int j = 4 * s + kq;
+                const double sj = wt[j];
+                const double ar = ybuf[j * D + r0 + i] * sj;
+                const double ai = ybuf[D2 + j * D + r0 + i] * sj;
+                const double br = ybuf[j * D + c0 + i] * sj;
+                const double bi = ybuf[D2 + j * D + c0 + i] * sj;
+                re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, re, 0, 0, 0);
+                re = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, im, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, im, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int a = r0 + kq + 4 * r, b = c0 + i;
+                const double v = a <= b ? re[r] : -im[r];
+                rp[4 * m + r] = v;
+                rhoP[a * D + b] = v;
+            }
+        }
+    } else if constexpr (RhoLayout<Q, G>::kMfma) {
         // rho = Zs Zs^dag with Zs = Z diag(sqrt w): Re rho = Zr Zr^T + Zi Zi^T and
         // Im rho = Zi Zr^T - Zr Zi^T, i.e. two 16x16 real products with K = 32,
         // eight v_mfma_f64_16x16x4f64 each.  Operand lane l carries

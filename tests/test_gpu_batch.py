@@ -13,7 +13,7 @@ from paper_2501_17334_amd import qst, synth
 
 pytestmark = pytest.mark.gpu
 
-BATCH_TEAM = {1: 8, 2: 16, 3: 32, 4: 64, 5: 512, 6: 512}
+BATCH_TEAM = {1: 8, 2: 16, 3: 32, 4: 64, 5: 256, 6: 512}
 
 
 @pytest.fixture(scope="module", autouse=True)

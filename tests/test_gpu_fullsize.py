@@ -1,0 +1,85 @@
+"""The 4-qubit benchmark workload at full size, in the launch configuration
+bench.py times: 65536 chains x 10^4 pCN steps in one launch (the tuned team
+shape), burn-in 2000, moments every step, 256 chains recorded every 8 steps.
+
+* Sampled chains (the first four, traced, and the last one) are replayed by
+  the oracle over all 10^4 steps: per-step log L within 1e-10 relative and
+  identical decisions up to the first near-tie, final states equal.
+* Properties that hold at any size: every chain stores exactly
+  n_steps - burn_in samples, the pooled mean is a density matrix (Hermitian,
+  unit trace, positive semidefinite), and the recorded trajectory of a traced
+  chain ends at its final packed rho.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2501_17334_amd import qst, synth
+from tests.gpu_util import first_near_step
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_fullsize_c3_sampled_chains():
+    prob = synth.make_problem("c3")
+    Q, R, NT, burn, beta = 4, prob.n_chains, 10000, 2000, 0.0063
+    assert R == 65536
+    k = 4
+    D = 2 ** Q
+    print(f"[fullsize] Q={Q} R={R} NT={NT} shape={qst.get_launch_shape(Q)}", flush=True)
+    P = qst.Problem(Q, prob.counts)
+    tr = dict(chains=k, llprop=torch.full((k, NT), float("nan"), dtype=torch.float64, device="cuda"),
+              logu=torch.zeros((k, NT), dtype=torch.float64, device="cuda"),
+              accept=torch.zeros((k, NT), dtype=torch.int8, device="cuda"))
+    rec = dict(every=8, chains=256,
+               buf=torch.zeros((256, NT // 8, D, D), dtype=torch.float64, device="cuda"))
+    cfg = qst.RunConfig(n_chains=R, n_steps=NT, seed=prob.seed, beta0=beta, burn_in=burn, adapt_every=500)
+    st = P.run(cfg, trace=tr, record=rec)
+    torch.cuda.synchronize()
+    assert st["proposed"] == R * NT
+    x, ll, b, nst = P.state()
+    assert np.all(nst == NT - burn)
+
+    print("[fullsize] oracle replay of the traced chains", flush=True)
+    ch = O.Chains(Q, prob.counts, O.RunParams(n_chains=k, n_steps=0, seed=prob.seed, beta0=beta, burn_in=burn,
+                                              adapt_every=500, trace_chains=k))
+    ll0 = ch.ll.copy()
+    o = ch.run(NT)
+    g_ll = tr["llprop"].cpu().numpy()
+    g_acc = tr["accept"].cpu().numpy()
+    stop = first_near_step(o["trace_llprop"], g_ll, o["trace_logu"], ll0, o["trace_accept"])
+    for r in range(k):
+        s = stop[r]
+        a, bb = o["trace_llprop"][r, :s], g_ll[r, :s]
+        assert np.all(np.abs(a - bb) <= 1e-10 * np.abs(a)), r
+        assert np.array_equal(o["trace_accept"][r, :s], g_acc[r, :s]), r
+        if s == NT:
+            assert np.allclose(x[r], ch.x[r], rtol=1e-9, atol=1e-9), r
+            assert b[r] == ch.beta[r]
+    print(f"[fullsize] traced chains compared over {stop.tolist()} steps", flush=True)
+
+    print("[fullsize] oracle replay of the last chain", flush=True)
+    last = O.Chains(Q, prob.counts, O.RunParams(n_chains=1, n_steps=0, seed=prob.seed, beta0=beta, burn_in=burn,
+                                                adapt_every=500, chain_offset=R - 1))
+    last.run(NT)
+    assert np.allclose(x[R - 1], last.x[0], rtol=1e-9, atol=1e-9)
+    assert abs(ll[R - 1] - last.ll[0]) <= 1e-10 * abs(last.ll[0])
+
+    pool = P.pool()
+    assert pool["n_samples"] == R * (NT - burn)
+    m = pool["mean"]
+    assert np.allclose(m, m.conj().T, atol=1e-14)
+    assert abs(np.trace(m).real - 1.0) < 1e-12
+    assert np.linalg.eigvalsh(m).min() > -1e-12
+    # the last record of chain 0 is its packed rho at step NT
+    r0 = rec["buf"][0, -1].cpu().numpy()
+    rho0 = O.rho_of_x(Q, x[0])
+    packed = O.pack(rho0)
+    assert np.allclose(r0, packed, atol=1e-12)
