@@ -200,23 +200,30 @@ __device__ __forceinline__ double team_sum(double v, double* scratch, int lane)
     }
 }
 
+// log L of a team from the lanes' shares (sum c e, sum c frac, any p <= 0 with
+// a count): one reduction of e ln2 + frac per lane, -inf if a lane saw a bad
+// probability.
 template <int G>
-__device__ __forceinline__ int team_or(int v, double* scratch, int lane)
+__device__ __forceinline__ double team_loglik(double part_e, double part_f, int bad, double* scratch, int lane)
+{
+    const double part = bad ? -INFINITY : __builtin_fma(part_e, kLn2, part_f);
+    return team_sum<G>(part, scratch, lane);
+}
+
+// Synchronisation of one team's LDS traffic.  A team of at most 64 lanes
+// lives inside one wavefront and its LDS region is its own; the LDS performs
+// a wavefront's operations in issue order, so ordering the compiler with a
+// wavefront-scope fence is enough and the team never waits for the other
+// wavefronts of its workgroup.  Wider teams take the workgroup barrier.
+template <int G>
+__device__ __forceinline__ void team_sync()
 {
     if constexpr (G <= 64) {
-#pragma unroll
-        for (int o = G / 2; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
-        return v;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
-        if ((lane & 63) == 0) scratch[8 + (lane >> 6)] = static_cast<double>(v);
         __syncthreads();
-        int s = 0;
-#pragma unroll
-        for (int w = 0; w < G / 64; ++w) s |= static_cast<int>(scratch[8 + w]);
-        __syncthreads();
-        return s;
     }
 }
 
@@ -402,7 +409,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
         }
     } else {
         stage_weights<Q, G, false>(ybuf, wt, lane);
-        __syncthreads();
+        team_sync<G>();
 #pragma unroll 1
         for (int e = 0; e < S::NPL; ++e) {
             const int p = lane + G * e;
@@ -822,28 +829,31 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     };
 
     // log L at the parameters in ybuf (team-uniform result); leaves packed rho in rhoP
+    // the dense contraction shares work across the workgroup's teams
+    auto sync = [&]() {
+        if constexpr (PATH == kPathDense) __syncthreads();
+        else team_sync<G>();
+    };
+
     auto evaluate = [&]() -> double {
         stage_rho<Q, G>(ybuf, wt, rhoP, rp, lane);
-        __syncthreads();
+        sync();
         if constexpr (PATH == kPathDense) {
             return dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, PATH>::kOffRed, A.mfrag, A.nd, logtab, tid);
         } else if constexpr (PREC == kPrecF32) {
             float* pauli32 = reinterpret_cast<float*>(pauli);
             stage_pauli_f32<Q, G>(rhoP, pauli32, lane);
-            __syncthreads();
+            sync();
             double part = 0.0;
             stage_loglik_f32<Q, G>(pauli32, A.nd, tables, lane, part);
             return kLn2 * team_sum<G>(part, misc + 4, lane);
         } else {
             stage_pauli<Q, G>(rhoP, pauli, lane);
-            __syncthreads();
+            sync();
             double part_e = 0.0, part_f = 0.0;
             int bad = 0;
             stage_loglik<Q, G>(pauli, A.nd, tables, lane, part_e, part_f, bad);
-            const double tot_e = team_sum<G>(part_e, misc + 4, lane);
-            const double tot_f = team_sum<G>(part_f, misc + 4, lane);
-            const int anybad = team_or<G>(bad, misc + 4, lane);
-            return anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
+            return team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
         }
     };
 
@@ -894,14 +904,14 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         const int64_t j = A.step_begin + 1 + t;
         const double a = sqrt(1.0 - beta * beta);
         draw(static_cast<uint64_t>(j));
-        __syncthreads();
+        sync();
         // pCN proposal y' = sqrt(1 - beta^2) y + beta eta, in place over eta
 #pragma unroll
         for (int e = 0; e < S::NYL; ++e) {
             const int i = lane + G * e;
             if (i < d) ybuf[i] = __builtin_fma(beta, ybuf[i], a * y[e]);
         }
-        __syncthreads();
+        sync();
         const double llp = evaluate();
         if (A.pair_every > 0 && live && chain < A.pair_chains && (t + 1) % A.pair_every == 0) {
             const int64_t slot = (t + 1) / A.pair_every - 1;   // rows are slot-major: [slot][chain]
@@ -960,7 +970,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
                 if (p < D2) dst[p] = rc[e];
             }
         }
-        __syncthreads();
+        sync();
     }
 
     // ---- write the state back ----
@@ -1053,10 +1063,8 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
         double part_e = 0.0, part_f = 0.0;
         int bad = 0;
         stage_loglik<Q, G>(pauli, nd, tables, lane, part_e, part_f, bad);
-        const double tot_e = team_sum<G>(part_e, misc + 4, lane);
-        const double tot_f = team_sum<G>(part_f, misc + 4, lane);
-        const int anybad = team_or<G>(bad, misc + 4, lane);
-        if (live && lane == 0) ll_out[idx] = anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
+        const double ll = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
+        if (live && lane == 0) ll_out[idx] = ll;
     }
 }
 

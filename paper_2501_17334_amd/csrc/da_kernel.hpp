@@ -189,10 +189,7 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_da_exact(DaAr
     double part_e = 0.0, part_f = 0.0;
     int bad = 0;
     stage_loglik<Q, G>(pauli, A.nd, tables, lane, part_e, part_f, bad);
-    const double tot_e = team_sum<G>(part_e, misc + 4, lane);
-    const double tot_f = team_sum<G>(part_f, misc + 4, lane);
-    const int anybad = team_or<G>(bad, misc + 4, lane);
-    const double llp = anybad ? -INFINITY : __builtin_fma(tot_e, kLn2, tot_f);
+    const double llp = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
     // teams without a survivor (the tail of the last workgroup) run along to
     // the barrier below but write nothing
     const double logu = fast_log(P.u_mh[c], logtab);
