@@ -200,6 +200,20 @@ __device__ __forceinline__ double team_sum(double v, double* scratch, int lane)
     }
 }
 
+// 1/sqrt(x) for x > 0 in FP64: the hardware reciprocal square root refined by
+// two Newton steps r <- r + r (1 - x r^2) / 2, which square its relative
+// error each time.
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = __builtin_fma(-x * r, r, 1.0);
+        r = __builtin_fma(0.5 * r, e, r);
+    }
+    return r;
+}
+
 // log L of a team from the lanes' shares (sum c e, sum c frac, any p <= 0 with
 // a count): one reduction of e ln2 + frac per lane, -inf if a lane saw a bad
 // probability.
@@ -387,7 +401,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
             nz += xor_lane<4>(nz);
             nz += xor_lane<8>(nz);
             const double v = ybuf[2 * D2 + j];
-            const double sj = sqrt((v * v / V) / nz);
+            const double sj = fabs(v) * rsqrt_f64(V * nz);   // sqrt(w_j)
             zr[t] *= sj;
             zi[t] *= sj;
         }
