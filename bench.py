@@ -259,17 +259,9 @@ def delayed_acceptance(qst, surrogate, synth, torch, np, name="c4", warm=4000, p
 def uneven_batch(qst, synth, torch, np, steps=20):
     """The 256-problem batch of 1..6 qubits (256..4096 chains each) as one
     persistent launch, against the same problems launched one after another
-    with their tuned shapes; both from step 0, the same streams, FP64."""
+    with their tuned shapes; both from step 0, the same streams, FP64.  Also
+    per qubit count: the problems of that size batched against solo."""
     probs = synth.mixed_batch(256)
-    cfgs = [qst.RunConfig(n_chains=p.n_chains, n_steps=steps, seed=p.seed, beta0=0.05, adapt_every=0)
-            for p in probs]
-    handles = [qst.Problem(p.n_qubits, p.counts) for p in probs]
-    work = sum(c.n_chains for c in cfgs) * steps
-    qst.run_batch(handles, [qst.RunConfig(n_chains=c.n_chains, n_steps=1, seed=c.seed, beta0=0.05) for c in cfgs],
-                  stats=False)
-    for h, c in zip(handles, cfgs):
-        h.run(qst.RunConfig(n_chains=min(c.n_chains, 256), n_steps=1, seed=c.seed, beta0=0.05), stats=False)
-    torch.cuda.synchronize()
 
     def timed(fn):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -279,18 +271,29 @@ def uneven_batch(qst, synth, torch, np, steps=20):
         torch.cuda.synchronize()
         return a.elapsed_time(b)
 
-    ms_batch = timed(lambda: qst.run_batch(handles, cfgs, stats=False))
-    ms_solo = timed(lambda: [h.run(c, stats=False) for h, c in zip(handles, cfgs)])
-    by_q = {}
-    for p in probs:
-        by_q[p.n_qubits] = by_q.get(p.n_qubits, 0) + 1
-    for h in handles:
-        h.close()
-    return {"workload": f"256 problems, qubits {dict(sorted(by_q.items()))}, 256..4096 chains each, "
-                        f"{steps} steps from step 0, FP64 Kronecker route",
-            "chain_steps": work, "batch_ms": ms_batch, "solo_ms": ms_solo,
-            "batch_chain_steps_per_s": work / (ms_batch / 1e3), "solo_chain_steps_per_s": work / (ms_solo / 1e3),
-            "speedup_vs_solo_launches": ms_solo / ms_batch}
+    def compare(ps):
+        cfgs = [qst.RunConfig(n_chains=p.n_chains, n_steps=steps, seed=p.seed, beta0=0.05, adapt_every=0)
+                for p in ps]
+        handles = [qst.Problem(p.n_qubits, p.counts) for p in ps]
+        work = sum(c.n_chains for c in cfgs) * steps
+        if len(handles) > 1:
+            qst.run_batch(handles, cfgs, stats=False)          # module load, buffers
+        for h, c in zip(handles, cfgs):
+            h.run(c, stats=False)
+        torch.cuda.synchronize()
+        ms_b = timed(lambda: qst.run_batch(handles, cfgs, stats=False)) if len(handles) > 1 else float("nan")
+        ms_s = timed(lambda: [h.run(c, stats=False) for h, c in zip(handles, cfgs)])
+        for h in handles:
+            h.close()
+        return {"problems": len(ps), "chain_steps": work, "batch_ms": ms_b, "solo_ms": ms_s,
+                "batch_chain_steps_per_s": work / (ms_b / 1e3), "solo_chain_steps_per_s": work / (ms_s / 1e3),
+                "speedup_vs_solo_launches": ms_s / ms_b}
+
+    out = {"workload": f"256 problems of 1..6 qubits, 256..4096 chains each, {steps} steps from step 0, "
+                       f"FP64 Kronecker route; one launch vs one launch per problem (tuned shapes)"}
+    out.update(compare(probs))
+    out["per_qubit_count"] = {str(q): compare([p for p in probs if p.n_qubits == q]) for q in range(1, 7)}
+    return out
 
 
 def pilot_beta(qst, P, seed, n_chains=256, n_steps=6000):
