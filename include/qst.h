@@ -61,20 +61,26 @@ typedef enum {
     QST_ERR_UNSUPPORTED = 5  /* valid but not implemented combination */
 } qst_status;
 
-/* Arithmetic of the probability contraction p = M vec(rho).  The sum
- * sum c log p and the acceptance test are FP64 in every mode. */
+/* Arithmetic of the probability contraction p = Tr(Lambda rho).  The
+ * count-weighted sum of log p and the acceptance test are FP64 in every
+ * mode; the chain state, rho and the moments are FP64 in every mode. */
 typedef enum {
     QST_FP64 = 0,     /* exact FP64 */
-    QST_FP32 = 1,     /* FP32 operands and accumulation, log p in FP64 */
-    QST_BF16X3 = 2    /* vec(rho) split into three BF16 parts against the exact BF16 M, FP32 accumulation */
+    QST_FP32 = 1,     /* dense: FP32 operands and accumulation, log p in FP64;
+                         Kronecker: FP32 Pauli coefficients, transforms and log2 p
+                         (hardware logarithm, p clamped at 2^-126), FP64 sum */
+    QST_BF16X3 = 2    /* dense only: vec(rho) split into three BF16 parts against
+                         the exact BF16 M, FP32 accumulation, log p in FP64 */
 } qst_precision;
 
 /* How p_kl = Tr(Lambda_kl rho) is formed. */
 typedef enum {
-    QST_PATH_AUTO = 0,   /* take the tuned choice for this Q (see qst_tune_*) */
-    QST_PATH_DENSE = 1,  /* GEMM of packed vec(rho) against the KD x D^2 Pauli matrix on MFMA */
-    QST_PATH_KRON = 2    /* per-qubit (Kronecker) route: Pauli coefficients, then a 2^Q-point
-                            Walsh-Hadamard transform per setting; FP64 only */
+    QST_PATH_AUTO = 0,   /* the Kronecker route, except for QST_BF16X3 (dense) */
+    QST_PATH_DENSE = 1,  /* GEMM of packed vec(rho) against the KD x D^2 Pauli matrix
+                            on MFMA; 1..4 qubits */
+    QST_PATH_KRON = 2    /* per-qubit (Kronecker) route: Pauli coefficients, then a
+                            2^Q-point Walsh-Hadamard transform per setting; FP64 or
+                            FP32 (QST_ERR_UNSUPPORTED for QST_BF16X3) */
 } qst_path;
 
 typedef struct qst_problem qst_problem;   /* opaque; owns every device buffer behind it */
