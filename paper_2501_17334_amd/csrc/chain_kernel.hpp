@@ -912,6 +912,14 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     }
 
     const int64_t n_rec = A.record_every > 0 ? A.n_steps / A.record_every : 0;
+    // Phases of the periodic events, advanced by one per step (no 64-bit
+    // division in the loop): j mod M_A, j mod T, (t + 1) mod record_every,
+    // (t + 1) mod pair_every, and the slot counters of the two recorders.
+    int64_t ph_adapt = A.adapt_every > 0 ? (A.step_begin + 1) % A.adapt_every : 1;
+    int64_t ph_thin = (A.step_begin + 1) % A.thin;
+    int32_t ph_rec = A.record_every > 0 ? 1 % A.record_every : 1;
+    int32_t ph_pair = A.pair_every > 0 ? 1 % A.pair_every : 1;
+    int64_t rec_slot = 0, pair_slot = 0;
 
     // ---- Algorithm 2 ----
     for (int64_t t = 0; t < A.n_steps; ++t) {
@@ -927,9 +935,8 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         }
         sync();
         const double llp = evaluate();
-        if (A.pair_every > 0 && live && chain < A.pair_chains && (t + 1) % A.pair_every == 0) {
-            const int64_t slot = (t + 1) / A.pair_every - 1;   // rows are slot-major: [slot][chain]
-            const int64_t row = slot * A.pair_chains + chain;
+        if (A.pair_every > 0 && live && chain < A.pair_chains && ph_pair == 0) {
+            const int64_t row = pair_slot * A.pair_chains + chain;   // rows are slot-major: [slot][chain]
             uint16_t* dst = A.pair_x + row * A.pair_width;
             for (int i = lane; i < A.pair_width; i += G) {
                 const float v = i < d ? static_cast<float>(ybuf[i]) : 0.0f;
@@ -953,7 +960,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             ++acc_w;
             ++nacc;
         }
-        if (A.adapt_every > 0 && j % A.adapt_every == 0) {
+        if (A.adapt_every > 0 && ph_adapt == 0) {
             if (A.adapt_until < 0 || j <= A.adapt_until) {
                 const double rate = static_cast<double>(acc_w) / static_cast<double>(A.adapt_every);
                 if (rate > A.adapt_hi) beta = fmin(beta * A.adapt_factor, 1.0);
@@ -961,7 +968,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             }
             acc_w = 0;
         }
-        if (j > A.burn_in && j % A.thin == 0) {
+        if (j > A.burn_in && ph_thin == 0) {
 #pragma unroll
             for (int e = 0; e < S::NPL; ++e) {
                 s1[e] += rc[e];
@@ -975,15 +982,20 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             if (A.tr_lu) A.tr_lu[o] = logu;
             if (A.tr_acc) A.tr_acc[o] = accept ? 1 : 0;
         }
-        if (A.record_every > 0 && live && chain < A.record_chains && (t + 1) % A.record_every == 0) {
-            const int64_t slot = (t + 1) / A.record_every - 1;
-            double* dst = A.rec + (chain * n_rec + slot) * D2;
+        if (A.record_every > 0 && live && chain < A.record_chains && ph_rec == 0) {
+            double* dst = A.rec + (chain * n_rec + rec_slot) * D2;
 #pragma unroll
             for (int e = 0; e < S::NPL; ++e) {
                 const int p = packed_slot<Q, G>(lane, e);
                 if (p < D2) dst[p] = rc[e];
             }
         }
+        if (ph_rec == 0) ++rec_slot;
+        if (ph_pair == 0) ++pair_slot;
+        if (++ph_adapt == A.adapt_every) ph_adapt = 0;
+        if (++ph_thin == A.thin) ph_thin = 0;
+        if (++ph_rec == A.record_every) ph_rec = 0;
+        if (++ph_pair == A.pair_every) ph_pair = 0;
         sync();
     }
 
