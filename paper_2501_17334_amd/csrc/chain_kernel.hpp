@@ -509,11 +509,12 @@ __device__ __forceinline__ void stage_pauli(const double* rhoP, double* pauli, i
         double im = (a == b) ? 0.0 : (a < b ? pim : -pim);
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
+            // upper butterfly output other - own, lower own + other
+            const uint32_t sg = ((a >> s) & 1u) << 31;
             const double ore = xor_lane_stage<Q>(re, s);
             const double oim = xor_lane_stage<Q>(im, s);
-            const bool up = (a >> s) & 1;
-            re = up ? ore - re : re + ore;
-            im = up ? oim - im : im + oim;
+            re = flip_sign(re, sg) + ore;
+            im = flip_sign(im, sg) + oim;
         }
         const int zy = a;
         const int r4 = __popc(m & zy) & 3;
@@ -545,11 +546,11 @@ __device__ __forceinline__ void stage_pauli_f32(const double* rhoP, float* pauli
         float im = (a == b) ? 0.0f : (a < b ? pim : -pim);
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
+            const uint32_t sg = ((a >> s) & 1u) << 31;
             const float ore = xor_lane_stage_f32(re, s);
             const float oim = xor_lane_stage_f32(im, s);
-            const bool up = (a >> s) & 1;
-            re = up ? ore - re : re + ore;
-            im = up ? oim - im : im + oim;
+            re = flip_sign(re, sg) + ore;
+            im = flip_sign(im, sg) + oim;
         }
         const int zy = a;
         const int r4 = __popc(m & zy) & 3;
@@ -584,7 +585,7 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
             const double other = xor_lane_stage<Q>(val, s);
-            val = ((i >> s) & 1) ? other - val : val + other;
+            val = flip_sign(val, ((i >> s) & 1u) << 31) + other;
         }
         const double p = val * (1.0 / D);
         const double n = valid ? nd[f] : 0.0;
@@ -621,7 +622,7 @@ __device__ __forceinline__ void stage_loglik_f32(const float* pauli, const doubl
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
             const float other = xor_lane_stage_f32(val, s);
-            val = ((i >> s) & 1) ? other - val : val + other;
+            val = flip_sign(val, ((i >> s) & 1u) << 31) + other;
         }
         const float p = fmaxf(val * (1.0f / D), 0x1.0p-126f);
         const double n = valid ? nd[f] : 0.0;
@@ -912,14 +913,6 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     }
 
     const int64_t n_rec = A.record_every > 0 ? A.n_steps / A.record_every : 0;
-    // Phases of the periodic events, advanced by one per step (no 64-bit
-    // division in the loop): j mod M_A, j mod T, (t + 1) mod record_every,
-    // (t + 1) mod pair_every, and the slot counters of the two recorders.
-    int64_t ph_adapt = A.adapt_every > 0 ? (A.step_begin + 1) % A.adapt_every : 1;
-    int64_t ph_thin = (A.step_begin + 1) % A.thin;
-    int32_t ph_rec = A.record_every > 0 ? 1 % A.record_every : 1;
-    int32_t ph_pair = A.pair_every > 0 ? 1 % A.pair_every : 1;
-    int64_t rec_slot = 0, pair_slot = 0;
 
     // ---- Algorithm 2 ----
     for (int64_t t = 0; t < A.n_steps; ++t) {
@@ -935,8 +928,9 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         }
         sync();
         const double llp = evaluate();
-        if (A.pair_every > 0 && live && chain < A.pair_chains && ph_pair == 0) {
-            const int64_t row = pair_slot * A.pair_chains + chain;   // rows are slot-major: [slot][chain]
+        if (A.pair_every > 0 && live && chain < A.pair_chains && (t + 1) % A.pair_every == 0) {
+            const int64_t slot = (t + 1) / A.pair_every - 1;   // rows are slot-major: [slot][chain]
+            const int64_t row = slot * A.pair_chains + chain;
             uint16_t* dst = A.pair_x + row * A.pair_width;
             for (int i = lane; i < A.pair_width; i += G) {
                 const float v = i < d ? static_cast<float>(ybuf[i]) : 0.0f;
@@ -960,7 +954,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             ++acc_w;
             ++nacc;
         }
-        if (A.adapt_every > 0 && ph_adapt == 0) {
+        if (A.adapt_every > 0 && j % A.adapt_every == 0) {
             if (A.adapt_until < 0 || j <= A.adapt_until) {
                 const double rate = static_cast<double>(acc_w) / static_cast<double>(A.adapt_every);
                 if (rate > A.adapt_hi) beta = fmin(beta * A.adapt_factor, 1.0);
@@ -968,7 +962,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             }
             acc_w = 0;
         }
-        if (j > A.burn_in && ph_thin == 0) {
+        if (j > A.burn_in && j % A.thin == 0) {
 #pragma unroll
             for (int e = 0; e < S::NPL; ++e) {
                 s1[e] += rc[e];
@@ -982,20 +976,15 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             if (A.tr_lu) A.tr_lu[o] = logu;
             if (A.tr_acc) A.tr_acc[o] = accept ? 1 : 0;
         }
-        if (A.record_every > 0 && live && chain < A.record_chains && ph_rec == 0) {
-            double* dst = A.rec + (chain * n_rec + rec_slot) * D2;
+        if (A.record_every > 0 && live && chain < A.record_chains && (t + 1) % A.record_every == 0) {
+            const int64_t slot = (t + 1) / A.record_every - 1;
+            double* dst = A.rec + (chain * n_rec + slot) * D2;
 #pragma unroll
             for (int e = 0; e < S::NPL; ++e) {
                 const int p = packed_slot<Q, G>(lane, e);
                 if (p < D2) dst[p] = rc[e];
             }
         }
-        if (ph_rec == 0) ++rec_slot;
-        if (ph_pair == 0) ++pair_slot;
-        if (++ph_adapt == A.adapt_every) ph_adapt = 0;
-        if (++ph_thin == A.thin) ph_thin = 0;
-        if (++ph_rec == A.record_every) ph_rec = 0;
-        if (++ph_pair == A.pair_every) ph_pair = 0;
         sync();
     }
 

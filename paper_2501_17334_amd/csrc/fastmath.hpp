@@ -120,9 +120,11 @@ __device__ __forceinline__ void sincospi_0_2(double x, double& s, double& c)
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
 {
+    // every source lane of the patterns used here exists, so the old value
+    // of the destination is never kept and needs no initialisation
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<uint32_t>(lo));
 }
 
@@ -148,11 +150,24 @@ __device__ __forceinline__ double xor_lane(double v)
     }
 }
 
+// -v if the sign mask is 0x80000000, v if it is 0 (one XOR of the sign bit).
+__device__ __forceinline__ double flip_sign(double v, uint32_t mask)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t hi = static_cast<uint32_t>(b >> 32) ^ mask;
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<uint32_t>(b));
+}
+
+__device__ __forceinline__ float flip_sign(float v, uint32_t mask)
+{
+    return __int_as_float(static_cast<int>(static_cast<uint32_t>(__float_as_int(v)) ^ mask));
+}
+
 // FP32 forms of the same lane exchanges (one 32-bit DPP move per step).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 template <int MASK>
