@@ -574,12 +574,20 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
     const LogEntry* tab = reinterpret_cast<const LogEntry*>(tables);
     const uint16_t* mutab = reinterpret_cast<const uint16_t*>(tables + WgTables<Q>::kLogDoubles);
     const int i = lane & (D - 1);  // position inside the D-lane group (= outcome l)
+    // the count of the next projector is loaded one iteration ahead (index
+    // clamped into range, value discarded where the projector does not exist)
+    double n_next = nd[lane < KD ? lane : 0];
 #pragma unroll 1
     for (int e = 0; e < S::NFL; ++e) {
         const int f = lane + G * e;
         const bool valid = (S::NFL * G == KD) || f < KD;
+        const double n_raw = n_next;
+        if (e + 1 < S::NFL) {
+            const int fn = f + G;
+            n_next = nd[fn < KD ? fn : 0];
+        }
         int mu;
-        if constexpr (WgTables<Q>::kMuTable) mu = valid ? mutab[f] : 0;
+        if constexpr (WgTables<Q>::kMuTable) mu = mutab[valid ? f : 0];
         else mu = valid ? pauli_index<Q>(f / D, i) : 0;
         double val = pauli[mu];
 #pragma unroll
@@ -588,7 +596,7 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
             val = flip_sign(val, ((i >> s) & 1u) << 31) + other;
         }
         const double p = val * (1.0 / D);
-        const double n = valid ? nd[f] : 0.0;
+        const double n = valid ? n_raw : 0.0;
         const bool pos = p > 0.0;
         bad |= (n > 0.0 && !pos) ? 1 : 0;
         int ex;
@@ -611,12 +619,18 @@ __device__ __forceinline__ void stage_loglik_f32(const float* pauli, const doubl
     constexpr int D = Dm::D, KD = Dm::KD;
     const uint16_t* mutab = reinterpret_cast<const uint16_t*>(tables + WgTables<Q>::kLogDoubles);
     const int i = lane & (D - 1);
+    double n_next = nd[lane < KD ? lane : 0];
 #pragma unroll 1
     for (int e = 0; e < S::NFL; ++e) {
         const int f = lane + G * e;
         const bool valid = (S::NFL * G == KD) || f < KD;
+        const double n_raw = n_next;
+        if (e + 1 < S::NFL) {
+            const int fn = f + G;
+            n_next = nd[fn < KD ? fn : 0];
+        }
         int mu;
-        if constexpr (WgTables<Q>::kMuTable) mu = valid ? mutab[f] : 0;
+        if constexpr (WgTables<Q>::kMuTable) mu = mutab[valid ? f : 0];
         else mu = valid ? pauli_index<Q>(f / D, i) : 0;
         float val = pauli[mu];
 #pragma unroll
@@ -625,7 +639,7 @@ __device__ __forceinline__ void stage_loglik_f32(const float* pauli, const doubl
             val = flip_sign(val, ((i >> s) & 1u) << 31) + other;
         }
         const float p = fmaxf(val * (1.0f / D), 0x1.0p-126f);
-        const double n = valid ? nd[f] : 0.0;
+        const double n = valid ? n_raw : 0.0;
         part = __builtin_fma(n, static_cast<double>(__builtin_amdgcn_logf(p)), part);
     }
 }

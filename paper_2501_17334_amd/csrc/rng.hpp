@@ -80,10 +80,13 @@ __device__ __forceinline__ Block4 stream_block(uint64_t seed, int tag, uint64_t 
 }
 
 // Uniform on the open interval (0,1): top 52 bits plus one half, times 2^-52
-// (exact in FP64, so the result is never 0 or 1).
+// (exact in FP64, so the result is never 0 or 1).  Formed without an integer
+// conversion: the 52 bits as the mantissa of a number x in [1, 2), then
+// x - (1 - 2^-53) = (m + 1/2) 2^-52 exactly.
 __device__ __forceinline__ double uniform_open(uint64_t w)
 {
-    return (static_cast<double>(w >> 12) + 0.5) * 0x1.0p-52;
+    const double x = __longlong_as_double(static_cast<long long>((w >> 12) | 0x3FF0000000000000ULL));
+    return x - 0x1.fffffffffffffp-1;
 }
 
 // Box-Muller (1958) on one pair of words: r = sqrt(-2 ln u_a),
