@@ -83,3 +83,67 @@ def test_fullsize_c3_sampled_chains():
     rho0 = O.rho_of_x(Q, x[0])
     packed = O.pack(rho0)
     assert np.allclose(r0, packed, atol=1e-12)
+
+
+def test_fullsize_c4_sampled_chains():
+    """The 5-qubit workload at its full chain count (16384) in the tuned
+    launch shape: chains 0, 1 (traced) and the last one replayed by the
+    oracle over 300 steps."""
+    prob = synth.make_problem("c4")
+    Q, R, NT, beta = 5, prob.n_chains, 300, 0.0063
+    assert R == 16384
+    k = 2
+    print(f"[fullsize c4] R={R} NT={NT} shape={qst.get_launch_shape(Q)}", flush=True)
+    P = qst.Problem(Q, prob.counts)
+    tr = dict(chains=k, llprop=torch.full((k, NT), float("nan"), dtype=torch.float64, device="cuda"),
+              logu=torch.zeros((k, NT), dtype=torch.float64, device="cuda"),
+              accept=torch.zeros((k, NT), dtype=torch.int8, device="cuda"))
+    P.run(qst.RunConfig(n_chains=R, n_steps=NT, seed=prob.seed, beta0=beta, adapt_every=100), trace=tr)
+    torch.cuda.synchronize()
+    x, ll, b, nst = P.state()
+    ch = O.Chains(Q, prob.counts, O.RunParams(n_chains=k, n_steps=0, seed=prob.seed, beta0=beta, adapt_every=100,
+                                              trace_chains=k))
+    ll0 = ch.ll.copy()
+    o = ch.run(NT)
+    g_ll = tr["llprop"].cpu().numpy()
+    stop = first_near_step(o["trace_llprop"], g_ll, o["trace_logu"], ll0, o["trace_accept"])
+    for r in range(k):
+        s = stop[r]
+        assert np.all(np.abs(o["trace_llprop"][r, :s] - g_ll[r, :s]) <= 1e-10 * np.abs(o["trace_llprop"][r, :s]))
+        if s == NT:
+            assert np.allclose(x[r], ch.x[r], rtol=1e-9, atol=1e-9)
+    last = O.Chains(Q, prob.counts, O.RunParams(n_chains=1, n_steps=0, seed=prob.seed, beta0=beta, adapt_every=100,
+                                                chain_offset=R - 1))
+    last.run(NT)
+    assert np.allclose(x[R - 1], last.x[0], rtol=1e-9, atol=1e-9)
+    print(f"[fullsize c4] compared over {stop.tolist()} steps and the last chain", flush=True)
+
+
+def test_fullsize_mixed_batch_sampled():
+    """The 256-problem mixed batch (1..6 qubits, 256..4096 chains each) in one
+    launch, as bench.py runs it (20 steps): for one problem of every qubit
+    count, its first and last chain (the last one only at 6 qubits) replayed
+    by the oracle."""
+    probs = synth.mixed_batch(256)
+    steps = 20
+    cfgs = [qst.RunConfig(n_chains=p.n_chains, n_steps=steps, seed=p.seed, beta0=0.05, adapt_every=0) for p in probs]
+    handles = [qst.Problem(p.n_qubits, p.counts) for p in probs]
+    print(f"[fullsize batch] {len(probs)} problems, {sum(c.n_chains for c in cfgs)} chains", flush=True)
+    st = qst.run_batch(handles, cfgs)
+    torch.cuda.synchronize()
+    assert all(s["proposed"] == c.n_chains * steps for s, c in zip(st, cfgs))
+    picked = {}
+    for idx, p in enumerate(probs):
+        picked.setdefault(p.n_qubits, idx)
+    for q, idx in sorted(picked.items()):
+        p, c, h = probs[idx], cfgs[idx], handles[idx]
+        x, ll, _, _ = h.state()
+        for chain in ((c.n_chains - 1,) if q == 6 else (0, c.n_chains - 1)):   # the oracle needs ~0.6 s per 6-qubit step
+            one = O.Chains(q, p.counts, O.RunParams(n_chains=1, n_steps=0, seed=p.seed, beta0=0.05, adapt_every=0,
+                                                    chain_offset=chain))
+            one.run(steps)
+            assert np.allclose(x[chain], one.x[0], rtol=1e-9, atol=1e-9), (q, idx, chain)
+            assert abs(ll[chain] - one.ll[0]) <= 1e-10 * abs(one.ll[0]), (q, idx, chain)
+        print(f"[fullsize batch] Q={q} problem {idx} ({c.n_chains} chains) ok", flush=True)
+    for h in handles:
+        h.close()
