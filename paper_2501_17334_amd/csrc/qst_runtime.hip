@@ -10,7 +10,9 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,6 +38,22 @@ struct QstError {
 void hip_check(hipError_t e, const char* what)
 {
     if (e != hipSuccess) fail(QST_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Dynamic LDS above the default limit must be allowed per kernel and per
+// device once; a larger request later raises the allowance.
+void allow_dynamic_lds(const void* kernel, size_t bytes)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> allowed;
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& cur = allowed[{kernel, dev}];
+    if (cur >= bytes) return;
+    hip_check(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)),
+              "hipFuncSetAttribute");
+    cur = bytes;
 }
 
 template <typename F>
@@ -201,13 +219,7 @@ void launch_chains_t(const qst::ChainArgs& a, hipStream_t s)
     const int64_t teams = WG / G;
     const int64_t blocks = (a.R + teams - 1) / teams;
     const size_t lds = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q, PATH>::kDoubles) * sizeof(double);
-    static bool attr_done = false;
-    if (!attr_done) {
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)),
-                  "hipFuncSetAttribute");
-        attr_done = true;
-    }
+    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many chains for one launch");
     hipLaunchKernelGGL((qst::k_chains<Q, G, WG, PATH, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s,
                        a);
@@ -221,13 +233,7 @@ void launch_loglik_dense_t(const double* nd, const void* mfrag, const double* rh
     using S = qst::TeamShape<Q, 64, qst::kPathDense>;
     const int64_t blocks = (n + 15) / 16;
     const size_t lds = (16 * static_cast<size_t>(S::kLds) + qst::WgTables<Q, qst::kPathDense>::kDoubles) * sizeof(double);
-    static bool attr_done = false;
-    if (!attr_done) {
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_loglik_dense<Q, PREC>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)),
-                  "hipFuncSetAttribute");
-        attr_done = true;
-    }
+    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_loglik_dense<Q, PREC>), lds);
     hipLaunchKernelGGL((qst::k_loglik_dense<Q, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(1024), lds, s, nd,
                        mfrag, rho, n, out);
     hip_check(hipGetLastError(), "dense loglik kernel launch");
@@ -240,13 +246,7 @@ void launch_loglik_t(const double* nd, const double* rho, int64_t n, double* out
     const int64_t teams = WG / G;
     const int64_t blocks = (n + teams - 1) / teams;
     const size_t lds = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q>::kDoubles) * sizeof(double);
-    static bool attr_done = false;
-    if (!attr_done) {
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_loglik<Q, G, WG, PREC>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)),
-                  "hipFuncSetAttribute");
-        attr_done = true;
-    }
+    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_loglik<Q, G, WG, PREC>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many states for one launch");
     hipLaunchKernelGGL((qst::k_loglik<Q, G, WG, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s, nd,
                        rho, n, out);
@@ -674,9 +674,7 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
                   "copy batch problems");
         hip_check(hipMemcpy(ditems, sorted.data(), sizeof(qst::BatchItem) * sorted.size(), hipMemcpyHostToDevice),
                   "copy batch tiles");
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_chains_batch),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)),
-                  "hipFuncSetAttribute");
+        allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_batch), lds);
         int dev = 0, n_cu = 0, per_cu = 0;
         hip_check(hipGetDevice(&dev), "hipGetDevice");
         hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
@@ -1295,16 +1293,8 @@ void da_steps(qst_problem* p, const qst_run_desc& r, qst_mlp* net, qst::DaArgs P
     const unsigned blocks = static_cast<unsigned>((p->R + teams - 1) / teams);
     const size_t lds_prop = (2 * qst::kLogTableSize + static_cast<size_t>(teams) * (Dm::d + 4)) * sizeof(double);
     const size_t lds_exact = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q>::kDoubles) * sizeof(double);
-    static bool attr_done = false;
-    if (!attr_done) {
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_da_propose<Q, G, WG>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_prop)),
-                  "hipFuncSetAttribute");
-        hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&qst::k_da_exact<Q, G, WG>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_exact)),
-                  "hipFuncSetAttribute");
-        attr_done = true;
-    }
+    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_da_propose<Q, G, WG>), lds_prop);
+    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_da_exact<Q, G, WG>), lds_exact);
     for (int64_t t = 0; t < r.n_steps; ++t) {
         P.j = p->step + 1 + t;
         P.t = t;
