@@ -41,9 +41,11 @@ def flops_per_chain_step(Q, stored_fraction):
 
 
 def kernel_source_hash():
+    """Hash of the sources the chain kernel is compiled from (its device
+    code: the step, the random numbers, the fast math)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2501_17334_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in ("chain_kernel.hpp", "fastmath.hpp", "rng.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
