@@ -262,7 +262,8 @@ def uneven_batch(qst, synth, torch, np, steps=20):
     """The 256-problem batch of 1..6 qubits (256..4096 chains each) as one
     persistent launch, against the same problems launched one after another
     with their tuned shapes; both from step 0, the same streams, FP64.  Also
-    per qubit count: the problems of that size batched against solo."""
+    per qubit count: the problems of that size batched against solo; and the
+    whole batch in the FP32 Kronecker form."""
     probs = synth.mixed_batch(256)
 
     def timed(fn):
@@ -273,10 +274,10 @@ def uneven_batch(qst, synth, torch, np, steps=20):
         torch.cuda.synchronize()
         return a.elapsed_time(b)
 
-    def compare(ps):
+    def compare(ps, precision="fp64"):
         cfgs = [qst.RunConfig(n_chains=p.n_chains, n_steps=steps, seed=p.seed, beta0=0.05, adapt_every=0)
                 for p in ps]
-        handles = [qst.Problem(p.n_qubits, p.counts) for p in ps]
+        handles = [qst.Problem(p.n_qubits, p.counts, precision=precision, path="kron") for p in ps]
         work = sum(c.n_chains for c in cfgs) * steps
         if len(handles) > 1:
             qst.run_batch(handles, cfgs, stats=False)          # module load, buffers
@@ -295,6 +296,11 @@ def uneven_batch(qst, synth, torch, np, steps=20):
                        f"FP64 Kronecker route; one launch vs one launch per problem (tuned shapes)"}
     out.update(compare(probs))
     out["per_qubit_count"] = {str(q): compare([p for p in probs if p.n_qubits == q]) for q in range(1, 7)}
+    # forms (1) and (2) together: the same batch with every problem in the FP32 Kronecker form
+    f32 = compare(probs, precision="fp32")
+    out["fp32_form"] = {k: f32[k] for k in ("batch_ms", "solo_ms", "batch_chain_steps_per_s",
+                                            "solo_chain_steps_per_s", "speedup_vs_solo_launches")}
+    out["fp32_form"]["batch_speedup_vs_fp64_batch"] = out["batch_ms"] / f32["batch_ms"]
     return out
 
 

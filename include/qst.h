@@ -172,8 +172,9 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out);
  * tiles, ordered largest-cost first, and taken from a device work counter by
  * resident workgroups; each problem's results are bit-identical to running
  * it alone with the same team size (qst_set_launch_shape), and equal up to
- * summation order otherwise.  Batches need the FP64 Kronecker path (QST_ERR_UNSUPPORTED
- * otherwise), distinct handles on one device, and use runs[0].stream.  A
+ * summation order otherwise.  Batches need the Kronecker path, FP64 or FP32
+ * per problem (QST_ERR_UNSUPPORTED otherwise), distinct handles on one
+ * device, and use runs[0].stream.  A
  * single-problem call returns without waiting unless stats is non-NULL; a
  * batch call waits for completion.  stats (host, [n_problems]) is filled
  * when non-NULL. */

@@ -630,11 +630,12 @@ size_t batch_lds_bytes(int Q)
     }
 }
 
-// Relative cost of one chain-step per qubit count (largest-first ordering of
-// batch tiles; only the order matters).
+// Cost of one chain-step per qubit count for the largest-first ordering of
+// batch tiles (ns of a full MI355X per chain-step, measured with the tuned
+// shapes; only the order matters).
 double chain_step_cost(int Q)
 {
-    static const double c[7] = {0.0, 1.0, 1.5, 3.0, 10.0, 60.0, 400.0};
+    static const double c[7] = {0.0, 0.16, 0.37, 1.6, 5.2, 32.0, 320.0};
     return c[Q];
 }
 
@@ -646,12 +647,13 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
     size_t lds = 0;
     for (int i = 0; i < n; ++i) {
         qst_problem* p = problems[i];
-        if (p->path != QST_PATH_KRON || p->precision != QST_FP64)
-            fail(QST_ERR_UNSUPPORTED, "batched launches use the FP64 Kronecker path");
+        if (p->path != QST_PATH_KRON)
+            fail(QST_ERR_UNSUPPORTED, "batched launches use the Kronecker path (FP64 or FP32)");
         args[i] = make_args(p, runs[i]);
         const int per = qst::kBatchWG / batch_team(p->Q);
+        const int32_t prec = p->precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64;
         for (int64_t c0 = 0; c0 < p->R; c0 += per) {
-            items.push_back({i, p->Q, c0});
+            items.push_back({i, p->Q, c0, prec, 0});
             cost.push_back(chain_step_cost(p->Q) * static_cast<double>(std::min<int64_t>(per, p->R - c0)) *
                            static_cast<double>(std::max<int64_t>(runs[i].n_steps, 1)));
         }

@@ -57,6 +57,34 @@ def test_batch_equals_solo():
             qst.set_launch_shape(q, *sh)
 
 
+def test_mixed_precision_batch_equals_solo():
+    """FP64 and FP32 Kronecker problems in one batch: each equals its solo
+    run in its own precision with the batch team size, bit for bit."""
+    probs = _problems()
+    precs = ["fp32", "fp64", "fp32", "fp64", "fp32", "fp32"]
+    chains = {1: 40, 2: 33, 3: 17, 4: 9, 5: 4, 6: 2}
+    steps = {1: 200, 2: 120, 3: 60, 4: 30, 5: 6, 6: 2}
+    cfgs = [qst.RunConfig(n_chains=chains[p.n_qubits], n_steps=steps[p.n_qubits], seed=p.seed + 5, beta0=0.05,
+                          adapt_every=20) for p in probs]
+    batch = [qst.Problem(p.n_qubits, p.counts, precision=pr, path="kron") for p, pr in zip(probs, precs)]
+    print("[batch mixed] run", flush=True)
+    qst.run_batch(batch, cfgs)
+    saved = {q: qst.get_launch_shape(q) for q in range(1, 7)}
+    try:
+        for q in range(1, 7):
+            qst.set_launch_shape(q, BATCH_TEAM[q], max(64, BATCH_TEAM[q]))
+        for p, pr, cfg, b in zip(probs, precs, cfgs, batch):
+            print(f"[batch mixed] solo Q={p.n_qubits} {pr}", flush=True)
+            solo = qst.Problem(p.n_qubits, p.counts, precision=pr, path="kron")
+            solo.run(cfg)
+            xs, lls, _, _ = solo.state()
+            xb, llb, _, _ = b.state()
+            assert np.array_equal(xs, xb) and np.array_equal(lls, llb), (p.n_qubits, pr)
+    finally:
+        for q, sh in saved.items():
+            qst.set_launch_shape(q, *sh)
+
+
 def test_batch_matches_oracle():
     """Every problem of a 1..6-qubit batch against the oracle: per-step log L
     of the proposals to 1e-10 relative while the decisions agree."""
