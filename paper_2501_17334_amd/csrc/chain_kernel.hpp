@@ -180,16 +180,24 @@ __device__ __forceinline__ void wg_tables_init(double* lds, int tid, int nthread
 // ---------------------------------------------------------------------------
 // team collectives (deterministic: every lane ends with the same bits)
 // ---------------------------------------------------------------------------
+// v + its partners across lane bits O, O/2, ..., 1 (in that order)
+template <int O>
+__device__ __forceinline__ double butterfly_sum(double v)
+{
+    v += xor_lane<O>(v);
+    if constexpr (O > 1) return butterfly_sum<O / 2>(v);
+    else return v;
+}
+
 template <int G>
 __device__ __forceinline__ double team_sum(double v, double* scratch, int lane)
 {
-    if constexpr (G <= 64) {
-#pragma unroll
-        for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if constexpr (G == 1) {
         return v;
+    } else if constexpr (G <= 64) {
+        return butterfly_sum<G / 2>(v);
     } else {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        v = butterfly_sum<32>(v);
         if ((lane & 63) == 0) scratch[lane >> 6] = v;
         __syncthreads();
         double s = 0.0;

@@ -134,6 +134,26 @@ constexpr int kDppQuadXor3 = 0x1B;     // quad_perm [3,2,1,0]
 constexpr int kDppRowMirror = 0x140;   // lane i <- lane 15-i within a row of 16 (xor 15)
 constexpr int kDppRowHalfMirror = 0x141;  // lane i <- lane 7-i within 8 (xor 7)
 
+// Exchange across 16- or 32-lane halves with the gfx950 lane-swap
+// instructions: permlane16_swap(v, v) leaves, in each 16-lane row, the
+// row's own values in the first result where the row index is odd and the
+// partner row's in the second where it is even (and the other way round);
+// permlane32_swap does the same for the two 32-lane halves.  The partner of
+// lane i is i ^ MASK.
+template <int MASK>
+__device__ __forceinline__ int xor_swap_i32(int v)
+{
+    static_assert(MASK == 16 || MASK == 32, "row or half swap");
+    const int lane = static_cast<int>(threadIdx.x) & 63;
+    if constexpr (MASK == 16) {
+        const auto q = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? q[0] : q[1];
+    } else {
+        const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? q[0] : q[1];
+    }
+}
+
 template <int MASK>
 __device__ __forceinline__ double xor_lane(double v)
 {
@@ -146,7 +166,10 @@ __device__ __forceinline__ double xor_lane(double v)
     } else if constexpr (MASK == 8) {
         return dpp_f64<kDppRowHalfMirror>(dpp_f64<kDppRowMirror>(v));  // (i^15)^7 = i^8
     } else {
-        return __shfl_xor(v, MASK, 64);
+        const long long b = __double_as_longlong(v);
+        const int lo = xor_swap_i32<MASK>(static_cast<int>(b));
+        const int hi = xor_swap_i32<MASK>(static_cast<int>(b >> 32));
+        return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<uint32_t>(lo));
     }
 }
 
@@ -182,7 +205,7 @@ __device__ __forceinline__ float xor_lane_f32(float v)
     } else if constexpr (MASK == 8) {
         return dpp_f32<kDppRowHalfMirror>(dpp_f32<kDppRowMirror>(v));
     } else {
-        return __shfl_xor(v, MASK, 64);
+        return __int_as_float(xor_swap_i32<MASK>(__float_as_int(v)));
     }
 }
 
