@@ -51,6 +51,7 @@ struct Dims {
 // Everything a chain launch needs; plain pointers into the problem's buffers.
 struct ChainArgs {
     const double* nd;       // [KD] counts as doubles
+    const uint16_t* mu;     // [KD] Pauli index of every (setting, transform position)
     const void* mfrag;      // dense path: the Pauli matrix in MFMA fragment order
     int64_t R;              // chains of the problem
     double* x;              // [R][d] current state
@@ -573,8 +574,8 @@ __device__ __forceinline__ void stage_pauli_f32(const double* rhoP, float* pauli
 // (sum c e, sum c frac) with log p = e ln2 + frac.
 template <int Q, int G>
 __device__ __forceinline__ void stage_loglik(const double* pauli, const double* __restrict__ nd,
-                                             const double* tables, int lane, double& part_e,
-                                             double& part_f, int& bad)
+                                             const uint16_t* __restrict__ mug, const double* tables, int lane,
+                                             double& part_e, double& part_f, int& bad)
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
@@ -584,19 +585,25 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
     const int i = lane & (D - 1);  // position inside the D-lane group (= outcome l)
     // the count of the next projector is loaded one iteration ahead (index
     // clamped into range, value discarded where the projector does not exist)
+    // the Pauli index comes from the LDS table where it fits, else from the
+    // problem's table in global memory, loaded one iteration ahead as well
+    constexpr bool kLdsMu = WgTables<Q>::kMuTable;
     double n_next = nd[lane < KD ? lane : 0];
+    int mu_next = kLdsMu ? 0 : mug[lane < KD ? lane : 0];
 #pragma unroll 1
     for (int e = 0; e < S::NFL; ++e) {
         const int f = lane + G * e;
         const bool valid = (S::NFL * G == KD) || f < KD;
         const double n_raw = n_next;
+        const int mu_raw = mu_next;
         if (e + 1 < S::NFL) {
             const int fn = f + G;
             n_next = nd[fn < KD ? fn : 0];
+            if constexpr (!kLdsMu) mu_next = mug[fn < KD ? fn : 0];
         }
         int mu;
-        if constexpr (WgTables<Q>::kMuTable) mu = mutab[valid ? f : 0];
-        else mu = valid ? pauli_index<Q>(f / D, i) : 0;
+        if constexpr (kLdsMu) mu = mutab[valid ? f : 0];
+        else mu = mu_raw;
         double val = pauli[mu];
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
@@ -620,26 +627,31 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
 // taken at that value.
 template <int Q, int G>
 __device__ __forceinline__ void stage_loglik_f32(const float* pauli, const double* __restrict__ nd,
-                                                 const double* tables, int lane, double& part)
+                                                 const uint16_t* __restrict__ mug, const double* tables, int lane,
+                                                 double& part)
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
     constexpr int D = Dm::D, KD = Dm::KD;
     const uint16_t* mutab = reinterpret_cast<const uint16_t*>(tables + WgTables<Q>::kLogDoubles);
     const int i = lane & (D - 1);
+    constexpr bool kLdsMu = WgTables<Q>::kMuTable;
     double n_next = nd[lane < KD ? lane : 0];
+    int mu_next = kLdsMu ? 0 : mug[lane < KD ? lane : 0];
 #pragma unroll 1
     for (int e = 0; e < S::NFL; ++e) {
         const int f = lane + G * e;
         const bool valid = (S::NFL * G == KD) || f < KD;
         const double n_raw = n_next;
+        const int mu_raw = mu_next;
         if (e + 1 < S::NFL) {
             const int fn = f + G;
             n_next = nd[fn < KD ? fn : 0];
+            if constexpr (!kLdsMu) mu_next = mug[fn < KD ? fn : 0];
         }
         int mu;
-        if constexpr (WgTables<Q>::kMuTable) mu = mutab[valid ? f : 0];
-        else mu = valid ? pauli_index<Q>(f / D, i) : 0;
+        if constexpr (kLdsMu) mu = mutab[valid ? f : 0];
+        else mu = mu_raw;
         float val = pauli[mu];
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
@@ -882,14 +894,14 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             stage_pauli_f32<Q, G>(rhoP, pauli32, lane);
             sync();
             double part = 0.0;
-            stage_loglik_f32<Q, G>(pauli32, A.nd, tables, lane, part);
+            stage_loglik_f32<Q, G>(pauli32, A.nd, A.mu, tables, lane, part);
             return kLn2 * team_sum<G>(part, misc + 4, lane);
         } else {
             stage_pauli<Q, G>(rhoP, pauli, lane);
             sync();
             double part_e = 0.0, part_f = 0.0;
             int bad = 0;
-            stage_loglik<Q, G>(pauli, A.nd, tables, lane, part_e, part_f, bad);
+            stage_loglik<Q, G>(pauli, A.nd, A.mu, tables, lane, part_e, part_f, bad);
             return team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
         }
     };
@@ -1062,8 +1074,8 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainA
 // Eq. (likelihood) for n given density matrices (complex, interleaved,
 // row-major), one team per matrix.
 template <int Q, int G, int WG, int PREC = kPrecF64>
-__global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, const double* rho,
-                                               int64_t n, double* ll_out)
+__global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, const uint16_t* __restrict__ mug,
+                                               const double* rho, int64_t n, double* ll_out)
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
@@ -1091,7 +1103,7 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
         stage_pauli_f32<Q, G>(rhoP, pauli32, lane);
         __syncthreads();
         double part = 0.0;
-        stage_loglik_f32<Q, G>(pauli32, nd, tables, lane, part);
+        stage_loglik_f32<Q, G>(pauli32, nd, mug, tables, lane, part);
         const double tot = team_sum<G>(part, misc + 4, lane);
         if (live && lane == 0) ll_out[idx] = kLn2 * tot;
     } else {
@@ -1099,7 +1111,7 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
         __syncthreads();
         double part_e = 0.0, part_f = 0.0;
         int bad = 0;
-        stage_loglik<Q, G>(pauli, nd, tables, lane, part_e, part_f, bad);
+        stage_loglik<Q, G>(pauli, nd, mug, tables, lane, part_e, part_f, bad);
         const double ll = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
         if (live && lane == 0) ll_out[idx] = ll;
     }

@@ -240,7 +240,8 @@ void launch_loglik_dense_t(const double* nd, const void* mfrag, const double* rh
 }
 
 template <int Q, int G, int WG, int PREC>
-void launch_loglik_t(const double* nd, const double* rho, int64_t n, double* out, hipStream_t s)
+void launch_loglik_t(const double* nd, const uint16_t* mu, const double* rho, int64_t n, double* out,
+                     hipStream_t s)
 {
     using S = qst::TeamShape<Q, G>;
     const int64_t teams = WG / G;
@@ -249,7 +250,7 @@ void launch_loglik_t(const double* nd, const double* rho, int64_t n, double* out
     allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_loglik<Q, G, WG, PREC>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many states for one launch");
     hipLaunchKernelGGL((qst::k_loglik<Q, G, WG, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s, nd,
-                       rho, n, out);
+                       mu, rho, n, out);
     hip_check(hipGetLastError(), "loglik kernel launch");
 }
 
@@ -295,23 +296,25 @@ void launch_loglik_dense(int Q, int prec, const double* nd, const void* mfrag, c
 }
 
 template <int PREC>
-void launch_loglik_p(int Q, const double* nd, const double* rho, int64_t n, double* out, hipStream_t s)
+void launch_loglik_p(int Q, const double* nd, const uint16_t* mu, const double* rho, int64_t n, double* out,
+                     hipStream_t s)
 {
     switch (Q) {
-        case 1: return launch_loglik_t<1, 8, 64, PREC>(nd, rho, n, out, s);
-        case 2: return launch_loglik_t<2, 16, 64, PREC>(nd, rho, n, out, s);
-        case 3: return launch_loglik_t<3, 32, 64, PREC>(nd, rho, n, out, s);
-        case 4: return launch_loglik_t<4, 64, 64, PREC>(nd, rho, n, out, s);
-        case 5: return launch_loglik_t<5, 64, 64, PREC>(nd, rho, n, out, s);
-        case 6: return launch_loglik_t<6, 256, 256, PREC>(nd, rho, n, out, s);
+        case 1: return launch_loglik_t<1, 8, 64, PREC>(nd, mu, rho, n, out, s);
+        case 2: return launch_loglik_t<2, 16, 64, PREC>(nd, mu, rho, n, out, s);
+        case 3: return launch_loglik_t<3, 32, 64, PREC>(nd, mu, rho, n, out, s);
+        case 4: return launch_loglik_t<4, 64, 64, PREC>(nd, mu, rho, n, out, s);
+        case 5: return launch_loglik_t<5, 64, 64, PREC>(nd, mu, rho, n, out, s);
+        case 6: return launch_loglik_t<6, 256, 256, PREC>(nd, mu, rho, n, out, s);
     }
     fail(QST_ERR_INVALID, "bad Q");
 }
 
-void launch_loglik(int Q, int prec, const double* nd, const double* rho, int64_t n, double* out, hipStream_t s)
+void launch_loglik(int Q, int prec, const double* nd, const uint16_t* mu, const double* rho, int64_t n, double* out,
+                   hipStream_t s)
 {
-    if (prec == qst::kPrecF32) return launch_loglik_p<qst::kPrecF32>(Q, nd, rho, n, out, s);
-    return launch_loglik_p<qst::kPrecF64>(Q, nd, rho, n, out, s);
+    if (prec == qst::kPrecF32) return launch_loglik_p<qst::kPrecF32>(Q, nd, mu, rho, n, out, s);
+    return launch_loglik_p<qst::kPrecF64>(Q, nd, mu, rho, n, out, s);
 }
 
 struct DeviceGuard {
@@ -332,6 +335,7 @@ struct qst_problem {
     qst_path path = QST_PATH_KRON;
     std::vector<int64_t> counts;
     double* nd = nullptr;  // counts as doubles
+    uint16_t* mu = nullptr;  // Pauli index of every (setting, transform position), [KD]
     void* mfrag[3] = {nullptr, nullptr, nullptr};  // dense path: Pauli matrix fragments per precision
 
     const void* fragments(int prec)
@@ -504,6 +508,21 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
         DeviceGuard g(p->device);
         p->nd = dev_alloc<double>(p->KD);
         hip_check(hipMemcpy(p->nd, nd.data(), sizeof(double) * p->KD, hipMemcpyHostToDevice), "copy counts");
+        // mu(k, t) = sum_q [t_q] (s_q(k) + 1) 4^(Q-1-q): the Pauli string whose
+        // coefficient enters position t of setting k's Walsh-Hadamard transform
+        std::vector<uint16_t> mu(p->KD);
+        for (int k = 0; k < p->K; ++k)
+            for (int t = 0; t < p->D; ++t) {
+                int m = 0, kk = k;
+                for (int q = Q - 1; q >= 0; --q) {
+                    const int digit = kk % 3;
+                    kk /= 3;
+                    if ((t >> (Q - 1 - q)) & 1) m += (digit + 1) << (2 * (Q - 1 - q));
+                }
+                mu[static_cast<size_t>(k) * p->D + t] = static_cast<uint16_t>(m);
+            }
+        p->mu = dev_alloc<uint16_t>(p->KD);
+        hip_check(hipMemcpy(p->mu, mu.data(), sizeof(uint16_t) * p->KD, hipMemcpyHostToDevice), "copy Pauli index");
         if (p->path == QST_PATH_DENSE) p->fragments(p->precision);
         *out = p.release();
     });
@@ -518,6 +537,7 @@ void qst_free_problem(qst_problem* p)
     if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
     p->free_state();
     dev_free(p->nd);
+    dev_free(p->mu);
     for (auto& f : p->mfrag) dev_free(f);
     (void)hipSetDevice(prev);
     delete p;
@@ -544,6 +564,7 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
 {
     qst::ChainArgs a{};
     a.nd = p->nd;
+    a.mu = p->mu;
     a.mfrag = p->path == QST_PATH_DENSE ? p->fragments(p->precision) : nullptr;
     a.R = p->R;
     a.x = p->x;
@@ -875,7 +896,7 @@ qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double
             const void* f = const_cast<qst_problem*>(p)->fragments(precision);
             launch_loglik_dense(p->Q, precision, p->nd, f, rho, n, ll_out, static_cast<hipStream_t>(stream));
         } else {
-            launch_loglik(p->Q, precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64, p->nd, rho, n, ll_out,
+            launch_loglik(p->Q, precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64, p->nd, p->mu, rho, n, ll_out,
                           static_cast<hipStream_t>(stream));
         }
     });
