@@ -138,44 +138,24 @@ struct TeamShape {
 };
 
 // Per-workgroup tables at the start of LDS, ahead of the teams: the
-// logarithm breakpoints and, when it fits, the Pauli index mu(k, t) of every
-// (setting, transform position) pair.
+// logarithm breakpoints (and, on the dense path, the per-wave partial
+// log-likelihoods).  The Pauli index of every (setting, transform position)
+// comes from a per-problem table in global memory (ChainArgs::mu), loaded one
+// iteration ahead in the likelihood loop; in LDS it would cost two dependent
+// reads per projector and, at 5 qubits, a quarter of the workgroup's LDS.
 template <int Q, int PATH = kPathKron>
 struct WgTables {
-    using Dm = Dims<Q>;
-    static constexpr bool kMuTable = PATH == kPathKron && Dm::KD * 2 <= 16384;
     static constexpr int kLogDoubles = 2 * kLogTableSize;
-    static constexpr int kMuDoubles = kMuTable ? (Dm::KD * 2 + 7) / 8 : 0;
     // dense path: per-wave partial log-likelihoods [16 waves][16 chains][3]
     static constexpr int kRedDoubles = PATH == kPathDense ? 16 * 16 * 3 : 0;
-    static constexpr int kOffRed = kLogDoubles + kMuDoubles;
+    static constexpr int kOffRed = kLogDoubles;
     static constexpr int kDoubles = kOffRed + kRedDoubles;
 };
-
-// mu(k, t) = sum_q [t_q] (s_q(k) + 1) 4^(Q-1-q): the Pauli string whose
-// coefficient enters position t of setting k's Walsh-Hadamard transform.
-template <int Q>
-__device__ __forceinline__ int pauli_index(int k, int t)
-{
-    int mu = 0, kk = k;
-#pragma unroll
-    for (int q = Q - 1; q >= 0; --q) {
-        const int s = kk % 3;
-        kk /= 3;
-        if ((t >> (Q - 1 - q)) & 1) mu += (s + 1) << (2 * (Q - 1 - q));
-    }
-    return mu;
-}
 
 template <int Q, int PATH = kPathKron>
 __device__ __forceinline__ void wg_tables_init(double* lds, int tid, int nthreads)
 {
-    using Dm = Dims<Q>;
     log_table_init(reinterpret_cast<LogEntry*>(lds), tid, nthreads);
-    if constexpr (WgTables<Q, PATH>::kMuTable) {
-        uint16_t* mu = reinterpret_cast<uint16_t*>(lds + WgTables<Q, PATH>::kLogDoubles);
-        for (int f = tid; f < Dm::KD; f += nthreads) mu[f] = static_cast<uint16_t>(pauli_index<Q>(f / Dm::D, f % Dm::D));
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -581,29 +561,23 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
     using S = TeamShape<Q, G>;
     constexpr int D = Dm::D, KD = Dm::KD;
     const LogEntry* tab = reinterpret_cast<const LogEntry*>(tables);
-    const uint16_t* mutab = reinterpret_cast<const uint16_t*>(tables + WgTables<Q>::kLogDoubles);
     const int i = lane & (D - 1);  // position inside the D-lane group (= outcome l)
-    // the count of the next projector is loaded one iteration ahead (index
-    // clamped into range, value discarded where the projector does not exist)
-    // the Pauli index comes from the LDS table where it fits, else from the
-    // problem's table in global memory, loaded one iteration ahead as well
-    constexpr bool kLdsMu = WgTables<Q>::kMuTable;
+    // the count and the Pauli index of the next projector are loaded one
+    // iteration ahead (index clamped into range, values discarded where the
+    // projector does not exist)
     double n_next = nd[lane < KD ? lane : 0];
-    int mu_next = kLdsMu ? 0 : mug[lane < KD ? lane : 0];
+    int mu_next = mug[lane < KD ? lane : 0];
 #pragma unroll 1
     for (int e = 0; e < S::NFL; ++e) {
         const int f = lane + G * e;
         const bool valid = (S::NFL * G == KD) || f < KD;
         const double n_raw = n_next;
-        const int mu_raw = mu_next;
+        const int mu = mu_next;
         if (e + 1 < S::NFL) {
             const int fn = f + G;
             n_next = nd[fn < KD ? fn : 0];
-            if constexpr (!kLdsMu) mu_next = mug[fn < KD ? fn : 0];
+            mu_next = mug[fn < KD ? fn : 0];
         }
-        int mu;
-        if constexpr (kLdsMu) mu = mutab[valid ? f : 0];
-        else mu = mu_raw;
         double val = pauli[mu];
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
@@ -633,25 +607,20 @@ __device__ __forceinline__ void stage_loglik_f32(const float* pauli, const doubl
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
     constexpr int D = Dm::D, KD = Dm::KD;
-    const uint16_t* mutab = reinterpret_cast<const uint16_t*>(tables + WgTables<Q>::kLogDoubles);
     const int i = lane & (D - 1);
-    constexpr bool kLdsMu = WgTables<Q>::kMuTable;
     double n_next = nd[lane < KD ? lane : 0];
-    int mu_next = kLdsMu ? 0 : mug[lane < KD ? lane : 0];
+    int mu_next = mug[lane < KD ? lane : 0];
 #pragma unroll 1
     for (int e = 0; e < S::NFL; ++e) {
         const int f = lane + G * e;
         const bool valid = (S::NFL * G == KD) || f < KD;
         const double n_raw = n_next;
-        const int mu_raw = mu_next;
+        const int mu = mu_next;
         if (e + 1 < S::NFL) {
             const int fn = f + G;
             n_next = nd[fn < KD ? fn : 0];
-            if constexpr (!kLdsMu) mu_next = mug[fn < KD ? fn : 0];
+            mu_next = mug[fn < KD ? fn : 0];
         }
-        int mu;
-        if constexpr (kLdsMu) mu = mutab[valid ? f : 0];
-        else mu = mu_raw;
         float val = pauli[mu];
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
