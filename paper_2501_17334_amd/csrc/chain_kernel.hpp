@@ -6,17 +6,19 @@
 // 64-wide wavefront, G = 128/256/512 spreads a large chain over several).
 // The chain state y (d = 2D^2+D doubles), the packed rho of the current
 // state and its moment sums stay in registers for the whole launch; the only
-// HBM traffic of the step loop is the count vector (read-only, L1/L2
-// resident) and the optional traces.  LDS holds, per team, the proposal y'
-// (read back as the matrix Z), the column weights, the packed rho' and the
-// Pauli coefficients.
+// global-memory traffic of the step loop is the count vector and the Pauli
+// index table (read-only, L2 resident) and the optional traces and records.
+// LDS holds, per team, the proposal y' (read back as the matrix Z), the
+// column weights, the packed rho' and the Pauli coefficients; per workgroup,
+// the logarithm table.  Teams of at most one wavefront synchronise with
+// wavefront-scope fences only.
 //
 // One step, per team (sections of the paper in brackets):
 //  1. Philox jobs: normal block b -> 4 normals of eta (Box-Muller), plus one
 //     job for the Metropolis-Hastings uniform; y' = sqrt(1-beta^2) y + beta eta
 //     [Alg. 2, proposal]
-//  2. w_j = v_j^2 / sum v^2 / |z_j|^2 and packed rho(y') = sum_j w_j z_j z_j^dag
-//     [parameterisation]
+//  2. w_j = v_j^2 / sum v^2 / |z_j|^2 and packed rho(y') = sum_j w_j z_j z_j^dag,
+//     on FP64 MFMA from 4 qubits up [parameterisation]
 //  3. Pauli coefficients c_mu = Tr(rho sigma_mu), 4^Q of them, each a signed
 //     sum of D entries of rho (sigma_mu has one non-zero per row)
 //  4. per setting k, p_kl = 2^-Q sum_t c_mu(k,t) (-1)^popcount(l&t): a
