@@ -41,14 +41,19 @@ def flops_per_chain_step(Q, stored_fraction):
 
 
 def kernel_source_hash():
-    """Hash of the sources the chain kernel is compiled from (its device
-    code: the step, the random numbers, the fast math)."""
+    """Hash of the code the chain kernel is compiled from (its device code:
+    the step, the random numbers, the fast math), comments and blank space
+    removed, so that only a change of code invalidates measured counters."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2501_17334_amd", "csrc")
     for name in ("chain_kernel.hpp", "fastmath.hpp", "rng.hpp"):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
+        with open(os.path.join(csrc, name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(name.encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
