@@ -269,8 +269,8 @@ __device__ __forceinline__ int packed_slot(int lane, int e)
 }
 
 // Column weights w_j = (v_j^2 / sum_k v_k^2) / |z_j|^2 from the parameters in
-// ybuf (x layout); the MFMA path stores sqrt(w_j) instead.
-template <int Q, int G, bool kSqrt>
+// ybuf (x layout).
+template <int Q, int G>
 __device__ __forceinline__ void stage_weights(const double* ybuf, double* wt, int lane)
 {
     using Dm = Dims<Q>;
@@ -290,7 +290,7 @@ __device__ __forceinline__ void stage_weights(const double* ybuf, double* wt, in
         }
         const double v = ybuf[2 * D2 + j];
         const double w = (v * v / V) / nz;
-        wt[j] = kSqrt ? sqrt(w) : w;
+        wt[j] = w;
     }
 }
 
@@ -413,7 +413,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
             rhoP[row * 16 + col] = v;
         }
     } else {
-        stage_weights<Q, G, false>(ybuf, wt, lane);
+        stage_weights<Q, G>(ybuf, wt, lane);
         team_sync<G>();
 #pragma unroll 1
         for (int e = 0; e < S::NPL; ++e) {

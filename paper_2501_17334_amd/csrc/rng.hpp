@@ -71,14 +71,6 @@ __device__ __forceinline__ Block4 philox4x64_10(uint64_t c0, uint64_t c1, uint64
     return b;
 }
 
-// Block `block` of stream `tag` for (chain, step): counter (block, step,
-// chain, tag << 56), key (seed, 0).
-__device__ __forceinline__ Block4 stream_block(uint64_t seed, int tag, uint64_t block, uint64_t step,
-                                               uint64_t chain)
-{
-    return philox4x64_10(block, step, chain, static_cast<uint64_t>(tag) << 56, seed, 0);
-}
-
 // Uniform on the open interval (0,1): top 52 bits plus one half, times 2^-52
 // (exact in FP64, so the result is never 0 or 1).  Formed without an integer
 // conversion: the 52 bits as the mantissa of a number x in [1, 2), then
