@@ -40,7 +40,7 @@ struct BatchTeam {
 template <int Q>
 constexpr size_t batch_lds_doubles()
 {
-    return static_cast<size_t>(kBatchWG / BatchTeam<Q>::G) * TeamShape<Q, BatchTeam<Q>::G>::kLds +
+    return static_cast<size_t>(kBatchWG / BatchTeam<Q>::G) * TeamShape<Q, BatchTeam<Q>::G>::kLdsChain +
            WgTables<Q>::kDoubles;
 }
 

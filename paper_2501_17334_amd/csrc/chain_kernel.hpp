@@ -137,6 +137,21 @@ struct TeamShape {
     // dense path: 16 teams are read side by side; a stride of 16k+1 doubles
     // keeps the 16 lanes of an MFMA column group on distinct LDS banks
     static constexpr int kLds = PATH == kPathDense ? (kLdsRaw + 14) / 16 * 16 + 1 : kLdsRaw;
+    // Philox jobs of a step: whole passes over the team, then a tail of kTail
+    // jobs.  On the Kronecker path the tails of kRing consecutive steps are
+    // drawn together in one pass into an LDS ring behind the team's area, so
+    // that a step does not pay a whole pass for a few lanes (kRing = 1: no
+    // ring).  kRing is capped so that the ring does not lower the number of
+    // workgroups per CU of the tuned launch shape (LDS is the limit there).
+    static constexpr int kJobs = Dm::NB + 1;
+    static constexpr int kFullJobs = kJobs / G * G;
+    static constexpr int kTail = kJobs - kFullJobs;
+    static constexpr int kRingCap = Q == 1 ? 2 : Q == 2 ? 3 : Q == 3 ? 10 : Q == 4 ? 6 : Q == 5 ? 18 : 30;
+    static constexpr int kRingFit = kTail > 0 ? G / kTail : 1;
+    static constexpr int kRing =
+        PATH == kPathKron && kTail > 0 ? (kRingFit < kRingCap ? kRingFit : kRingCap) : 1;
+    static constexpr int kRingDoubles = kRing > 1 ? 4 * kTail * kRing : 0;
+    static constexpr int kLdsChain = kLds + kRingDoubles;   // per team, in the chain kernels
 };
 
 // Per-workgroup tables at the start of LDS, ahead of the teams: the
@@ -807,7 +822,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     const int64_t c = live ? chain : 0;
 
     const LogEntry* logtab = reinterpret_cast<const LogEntry*>(tables);
-    double* base = lds + team * S::kLds;
+    double* base = lds + team * S::kLdsChain;
     double* ybuf = base;                 // proposal y' (x layout), kept until the decision
     double* pauli = base + S::kOffPauli;
     double* rhoP = base + S::kOffRho;
@@ -821,29 +836,88 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     int acc_w;
     int64_t nst, nacc = 0, nnear = 0;
 
-    // Philox jobs of one step: normal block b -> eta[4b..4b+3] into ybuf,
-    // job NB -> the Metropolis-Hastings uniform into misc[0]
-    auto draw = [&](uint64_t step) {
+    // Philox job `job` of step `step`: normal block b -> eta[4b..4b+3], job
+    // NB -> the Metropolis-Hastings uniform (in v[0])
+    auto job_values = [&](int job, uint64_t step, double v[4]) {
+        const bool normal = job < NB;
+        const uint64_t c0 = normal ? static_cast<uint64_t>(job) : 0;
+        const uint64_t c3 = normal ? 0 : (static_cast<uint64_t>(kTagMH) << 56);
+        const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(c), c3, A.seed, 0);
+        if (normal) {
+            box_muller(B.w[0], B.w[1], v[0], v[1], logtab);
+            box_muller(B.w[2], B.w[3], v[2], v[3], logtab);
+        } else {
+            v[0] = uniform_open(B.w[0]);
+            v[1] = v[2] = v[3] = 0.0;
+        }
+    };
+    // eta into ybuf, the uniform into misc[0]
+    auto store_job = [&](int job, const double v[4]) {
+        if (job < NB) {
+            const int i = 4 * job;
+            ybuf[i] = v[0];
+            if (i + 1 < d) ybuf[i + 1] = v[1];
+            if (i + 2 < d) ybuf[i + 2] = v[2];
+            if (i + 3 < d) ybuf[i + 3] = v[3];
+        } else {
+            misc[0] = v[0];
+        }
+    };
+
+    // every job of one step
+    auto draw_all = [&](uint64_t step) {
 #pragma unroll 1
         for (int e = 0; e < S::NJL; ++e) {
             const int job = lane + G * e;
-            const bool normal = job < NB;
             if (job <= NB) {
-                const uint64_t c0 = normal ? static_cast<uint64_t>(job) : 0;
-                const uint64_t c3 = normal ? 0 : (static_cast<uint64_t>(kTagMH) << 56);
-                const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(c), c3, A.seed, 0);
-                if (normal) {
-                    double n0, n1, n2, n3;
-                    box_muller(B.w[0], B.w[1], n0, n1, logtab);
-                    box_muller(B.w[2], B.w[3], n2, n3, logtab);
-                    const int i = 4 * job;
-                    ybuf[i] = n0;
-                    if (i + 1 < d) ybuf[i + 1] = n1;
-                    if (i + 2 < d) ybuf[i + 2] = n2;
-                    if (i + 3 < d) ybuf[i + 3] = n3;
-                } else {
-                    misc[0] = uniform_open(B.w[0]);
+                double v[4];
+                job_values(job, step, v);
+                store_job(job, v);
+            }
+        }
+    };
+
+    // one step in the loop; k = position of the step in its ring group (the
+    // group's tails are drawn at k = 0 for steps step .. step + kRing - 1)
+    double* ring = base + S::kLds;
+    auto draw = [&](uint64_t step, int k) {
+#pragma unroll 1
+        for (int e = 0; e < S::kFullJobs / G; ++e) {
+            const int job = lane + G * e;
+            double v[4];
+            job_values(job, step, v);
+            store_job(job, v);
+        }
+        if constexpr (S::kTail > 0 && S::kRing > 1) {
+            if (k == 0) {
+                if (lane < S::kTail * S::kRing) {
+                    // ring[(k' kTail + r) 4 + m] = value m of tail job r of step + k'
+                    double v[4];
+                    job_values(S::kFullJobs + lane % S::kTail, step + static_cast<uint64_t>(lane / S::kTail), v);
+                    double* dst = ring + 4 * lane;
+                    dst[0] = v[0];
+                    dst[1] = v[1];
+                    dst[2] = v[2];
+                    dst[3] = v[3];
                 }
+                team_sync<G>();
+            }
+            for (int m = lane; m < 4 * S::kTail; m += G) {   // 4 kTail can exceed a small team
+                const double v = ring[4 * S::kTail * k + m];
+                const int job = S::kFullJobs + m / 4;
+                const int i = 4 * S::kFullJobs + m;
+                if (job < NB) {
+                    if (i < d) ybuf[i] = v;
+                } else if ((m & 3) == 0) {
+                    misc[0] = v;
+                }
+            }
+        } else if constexpr (S::kTail > 0) {
+            if (lane < S::kTail) {
+                const int job = S::kFullJobs + lane;
+                double v[4];
+                job_values(job, step, v);
+                store_job(job, v);
             }
         }
     };
@@ -879,7 +953,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
 
     // ---- load or initialise the chain state ----
     if (A.init) {
-        draw(0);                         // y^0 ~ N(0, I): Algorithm 2, first line
+        draw_all(0);                     // y^0 ~ N(0, I): Algorithm 2, first line
         __syncthreads();
         ll = evaluate();
 #pragma unroll
@@ -920,10 +994,12 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     const int64_t n_rec = A.record_every > 0 ? A.n_steps / A.record_every : 0;
 
     // ---- Algorithm 2 ----
+    int kr = 0;   // position of the step in its group of kRing steps
     for (int64_t t = 0; t < A.n_steps; ++t) {
         const int64_t j = A.step_begin + 1 + t;
         const double a = sqrt(1.0 - beta * beta);
-        draw(static_cast<uint64_t>(j));
+        draw(static_cast<uint64_t>(j), kr);
+        kr = kr + 1 == S::kRing ? 0 : kr + 1;
         sync();
         // pCN proposal y' = sqrt(1 - beta^2) y + beta eta, in place over eta
 #pragma unroll

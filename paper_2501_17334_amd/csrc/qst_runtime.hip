@@ -218,7 +218,7 @@ void launch_chains_t(const qst::ChainArgs& a, hipStream_t s)
     using S = qst::TeamShape<Q, G, PATH>;
     const int64_t teams = WG / G;
     const int64_t blocks = (a.R + teams - 1) / teams;
-    const size_t lds = (static_cast<size_t>(teams) * S::kLds + qst::WgTables<Q, PATH>::kDoubles) * sizeof(double);
+    const size_t lds = (static_cast<size_t>(teams) * S::kLdsChain + qst::WgTables<Q, PATH>::kDoubles) * sizeof(double);
     allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many chains for one launch");
     hipLaunchKernelGGL((qst::k_chains<Q, G, WG, PATH, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s,
