@@ -9,8 +9,9 @@
 // global-memory traffic of the step loop is the count vector and the Pauli
 // index table (read-only, L2 resident) and the optional traces and records.
 // LDS holds, per team, the proposal y' (read back as the matrix Z), the
-// column weights, the packed rho' and the Pauli coefficients; per workgroup,
-// the logarithm table.  Teams of at most one wavefront synchronise with
+// column weights, the packed rho', the Pauli coefficients and a ring of
+// Philox values drawn ahead for the next steps; per workgroup, the logarithm
+// table.  Teams of at most one wavefront synchronise with
 // wavefront-scope fences only.
 //
 // One step, per team (sections of the paper in brackets):
@@ -864,7 +865,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         }
     };
 
-    // every job of one step
+    // every job of one step, directly
     auto draw_all = [&](uint64_t step) {
 #pragma unroll 1
         for (int e = 0; e < S::NJL; ++e) {
@@ -877,18 +878,24 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         }
     };
 
-    // one step in the loop; k = position of the step in its ring group (the
-    // group's tails are drawn at k = 0 for steps step .. step + kRing - 1)
+    // One step of the loop.  Without a ring: draw_all.  With one: the whole
+    // passes, then at k = 0 (the first step of a group of kRing) one pass
+    // draws the tails of steps step .. step + kRing - 1 into the ring, and
+    // every step copies its own tail (k = its position in the group) into
+    // place.  Separate loops for the two cases: one loop with a ring pass
+    // folded in spills more and runs slower.
     double* ring = base + S::kLds;
     auto draw = [&](uint64_t step, int k) {
+        if constexpr (S::kRing == 1) {
+            draw_all(step);
+        } else {
 #pragma unroll 1
-        for (int e = 0; e < S::kFullJobs / G; ++e) {
-            const int job = lane + G * e;
-            double v[4];
-            job_values(job, step, v);
-            store_job(job, v);
-        }
-        if constexpr (S::kTail > 0 && S::kRing > 1) {
+            for (int e = 0; e < S::kFullJobs / G; ++e) {
+                const int job = lane + G * e;
+                double v[4];
+                job_values(job, step, v);
+                store_job(job, v);
+            }
             if (k == 0) {
                 if (lane < S::kTail * S::kRing) {
                     // ring[(k' kTail + r) 4 + m] = value m of tail job r of step + k'
@@ -911,13 +918,6 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
                 } else if ((m & 3) == 0) {
                     misc[0] = v;
                 }
-            }
-        } else if constexpr (S::kTail > 0) {
-            if (lane < S::kTail) {
-                const int job = S::kFullJobs + lane;
-                double v[4];
-                job_values(job, step, v);
-                store_job(job, v);
             }
         }
     };
