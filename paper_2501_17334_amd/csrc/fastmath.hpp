@@ -131,8 +131,8 @@ __device__ __forceinline__ double dpp_f64(double v)
 constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
 constexpr int kDppQuadXor3 = 0x1B;     // quad_perm [3,2,1,0]
-constexpr int kDppRowMirror = 0x140;   // lane i <- lane 15-i within a row of 16 (xor 15)
 constexpr int kDppRowHalfMirror = 0x141;  // lane i <- lane 7-i within 8 (xor 7)
+constexpr int kDppRowRor8 = 0x128;     // rotate a row of 16 by 8: lane i <- lane (i + 8) mod 16 = i ^ 8
 
 // Exchange across 16- or 32-lane halves with the gfx950 lane-swap
 // instructions: permlane16_swap(v, v) leaves, in each 16-lane row, the
@@ -164,7 +164,7 @@ __device__ __forceinline__ double xor_lane(double v)
     } else if constexpr (MASK == 4) {
         return dpp_f64<kDppRowHalfMirror>(dpp_f64<kDppQuadXor3>(v));   // (i^3)^7 = i^4
     } else if constexpr (MASK == 8) {
-        return dpp_f64<kDppRowHalfMirror>(dpp_f64<kDppRowMirror>(v));  // (i^15)^7 = i^8
+        return dpp_f64<kDppRowRor8>(v);
     } else {
         const long long b = __double_as_longlong(v);
         const int lo = xor_swap_i32<MASK>(static_cast<int>(b));
@@ -203,7 +203,7 @@ __device__ __forceinline__ float xor_lane_f32(float v)
     } else if constexpr (MASK == 4) {
         return dpp_f32<kDppRowHalfMirror>(dpp_f32<kDppQuadXor3>(v));
     } else if constexpr (MASK == 8) {
-        return dpp_f32<kDppRowHalfMirror>(dpp_f32<kDppRowMirror>(v));
+        return dpp_f32<kDppRowRor8>(v);
     } else {
         return __int_as_float(xor_swap_i32<MASK>(__float_as_int(v)));
     }
