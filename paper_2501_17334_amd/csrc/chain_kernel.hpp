@@ -55,6 +55,8 @@ struct Dims {
 struct ChainArgs {
     const double* nd;       // [KD] counts as doubles
     const uint16_t* mu;     // [KD] Pauli index of every (setting, transform position)
+    const double* ndv;      // [KD] counts, task-major order of the likelihood transforms (LikSplit)
+    const uint16_t* muv;    // [KD] Pauli indices in the same order
     const void* mfrag;      // dense path: the Pauli matrix in MFMA fragment order
     int64_t R;              // chains of the problem
     double* x;              // [R][d] current state
@@ -567,49 +569,124 @@ __device__ __forceinline__ void stage_pauli_f32(const double* rhoP, float* pauli
     }
 }
 
+// Work split of the per-setting transforms.  A lane holds V = min(4, D)
+// positions t = tl + L j (j < V) of one setting, L = D / V lanes per
+// setting, so the top log2 V butterfly stages are register adds and only the
+// lower ones cross lanes.  Task u = k L + tl covers setting k; the counts and
+// Pauli indices are also stored task-major (ndv, muv: entry u V + j is
+// position tl + L j of setting k), so a lane loads its V entries at once.
+// Settings left over after the passes in which every lane is busy run in the
+// one-value layout (D lanes per setting, entries nd / mu in natural order)
+// when they fit one pass of it, else as a last partial pass of tasks.
+template <int Q, int G>
+struct LikSplit {
+    static constexpr int D = 1 << Q, K = pow3(Q), KD = K * D;
+    static constexpr int V = D < 4 ? D : 4;
+    static constexpr int L = D / V;
+    static constexpr int kLogL = L == 1 ? 0 : L == 2 ? 1 : L == 4 ? 2 : L == 8 ? 3 : 4;
+    static constexpr int kTasks = K * L;
+    static constexpr int kWhole = kTasks / G;
+    static constexpr int kRemSettings = (kTasks - kWhole * G) / L;
+    static constexpr bool kRemFlat = kRemSettings > 0 && kRemSettings * D <= G;
+    static constexpr int kPasses = kWhole + (kRemSettings > 0 && !kRemFlat ? 1 : 0);
+    static constexpr int kFlat0 = kWhole * (G / L);   // first setting of the one-value pass
+    static_assert(G % L == 0, "a team holds whole settings");
+};
+
+// In-register butterflies over the V values of a lane (positions bits
+// kLogL, kLogL + 1): lower output a + b, upper a - b.
+template <int V, typename T>
+__device__ __forceinline__ void wht_in_lane(T (&v)[V])
+{
+    if constexpr (V >= 2) {
+#pragma unroll
+        for (int j = 0; j < V; j += 2) {
+            const T a = v[j], b = v[j + 1];
+            v[j] = a + b;
+            v[j + 1] = a - b;
+        }
+    }
+    if constexpr (V == 4) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const T a = v[j], b = v[j + 2];
+            v[j] = a + b;
+            v[j + 2] = a - b;
+        }
+    }
+}
+
 // Probabilities of every projector by a 2^Q-point Walsh-Hadamard transform
-// per setting across lanes, and this lane's share of sum c log p, kept as
+// per setting, and this lane's share of sum c log p, kept as
 // (sum c e, sum c frac) with log p = e ln2 + frac.
 template <int Q, int G>
 __device__ __forceinline__ void stage_loglik(const double* pauli, const double* __restrict__ nd,
-                                             const uint16_t* __restrict__ mug, const double* tables, int lane,
+                                             const uint16_t* __restrict__ mug, const double* __restrict__ ndv,
+                                             const uint16_t* __restrict__ muv, const double* tables, int lane,
                                              double& part_e, double& part_f, int& bad)
 {
-    using Dm = Dims<Q>;
-    using S = TeamShape<Q, G>;
-    constexpr int D = Dm::D, KD = Dm::KD;
+    using LS = LikSplit<Q, G>;
+    constexpr int D = LS::D, V = LS::V, L = LS::L;
     const LogEntry* tab = reinterpret_cast<const LogEntry*>(tables);
-    const int i = lane & (D - 1);  // position inside the D-lane group (= outcome l)
-    // the count and the Pauli index of the next projector are loaded one
-    // iteration ahead (index clamped into range, values discarded where the
-    // projector does not exist)
-    double n_next = nd[lane < KD ? lane : 0];
-    int mu_next = mug[lane < KD ? lane : 0];
-#pragma unroll 1
-    for (int e = 0; e < S::NFL; ++e) {
-        const int f = lane + G * e;
-        const bool valid = (S::NFL * G == KD) || f < KD;
-        const double n_raw = n_next;
-        const int mu = mu_next;
-        if (e + 1 < S::NFL) {
-            const int fn = f + G;
-            n_next = nd[fn < KD ? fn : 0];
-            mu_next = mug[fn < KD ? fn : 0];
-        }
-        double val = pauli[mu];
-#pragma unroll
-        for (int s = 0; s < Q; ++s) {
-            const double other = xor_lane_stage<Q>(val, s);
-            val = flip_sign(val, ((i >> s) & 1u) << 31) + other;
-        }
+    auto term = [&](double val, double n) {
         const double p = val * (1.0 / D);
-        const double n = valid ? n_raw : 0.0;
         const bool pos = p > 0.0;
         bad |= (n > 0.0 && !pos) ? 1 : 0;
         int ex;
         const double fr = log_parts(pos ? p : 1.0, tab, ex);
         part_e = __builtin_fma(n, static_cast<double>(ex), part_e);
         part_f = __builtin_fma(n, fr, part_f);
+    };
+    const int tl = lane & (L - 1);
+    if constexpr (LS::kPasses > 0) {
+        // indices of the next task loaded one pass ahead (clamped into range)
+        uint16_t mu_next[V];
+        {
+            const int u = lane < LS::kTasks ? lane : 0;
+#pragma unroll
+            for (int j = 0; j < V; ++j) mu_next[j] = muv[u * V + j];
+        }
+#pragma unroll 1
+        for (int e = 0; e < LS::kPasses; ++e) {
+            const int u = lane + G * e;
+            const bool valid = LS::kPasses * G <= LS::kTasks || u < LS::kTasks;
+            const int uc = valid ? u : 0;
+            double n[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) n[j] = ndv[uc * V + j];
+            double v[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = pauli[mu_next[j]];
+            if (e + 1 < LS::kPasses) {
+                const int un = u + G < LS::kTasks ? u + G : 0;
+#pragma unroll
+                for (int j = 0; j < V; ++j) mu_next[j] = muv[un * V + j];
+            }
+#pragma unroll
+            for (int s = 0; s < LS::kLogL; ++s) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const double other = xor_lane_stage<Q>(v[j], s);
+                    v[j] = flip_sign(v[j], ((tl >> s) & 1u) << 31) + other;
+                }
+            }
+            wht_in_lane<V>(v);
+#pragma unroll
+            for (int j = 0; j < V; ++j) term(v[j], valid ? n[j] : 0.0);
+        }
+    }
+    if constexpr (LS::kRemFlat) {
+        const int i = lane & (D - 1);
+        const bool valid = lane < (LS::K - LS::kFlat0) * D;
+        const int f = valid ? LS::kFlat0 * D + lane : 0;
+        const double n = nd[f];
+        double val = pauli[mug[f]];
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const double other = xor_lane_stage<Q>(val, s);
+            val = flip_sign(val, ((i >> s) & 1u) << 31) + other;
+        }
+        term(val, valid ? n : 0.0);
     }
 }
 
@@ -619,35 +696,64 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
 // taken at that value.
 template <int Q, int G>
 __device__ __forceinline__ void stage_loglik_f32(const float* pauli, const double* __restrict__ nd,
-                                                 const uint16_t* __restrict__ mug, const double* tables, int lane,
-                                                 double& part)
+                                                 const uint16_t* __restrict__ mug, const double* __restrict__ ndv,
+                                                 const uint16_t* __restrict__ muv, int lane, double& part)
 {
-    using Dm = Dims<Q>;
-    using S = TeamShape<Q, G>;
-    constexpr int D = Dm::D, KD = Dm::KD;
-    const int i = lane & (D - 1);
-    double n_next = nd[lane < KD ? lane : 0];
-    int mu_next = mug[lane < KD ? lane : 0];
-#pragma unroll 1
-    for (int e = 0; e < S::NFL; ++e) {
-        const int f = lane + G * e;
-        const bool valid = (S::NFL * G == KD) || f < KD;
-        const double n_raw = n_next;
-        const int mu = mu_next;
-        if (e + 1 < S::NFL) {
-            const int fn = f + G;
-            n_next = nd[fn < KD ? fn : 0];
-            mu_next = mug[fn < KD ? fn : 0];
+    using LS = LikSplit<Q, G>;
+    constexpr int D = LS::D, V = LS::V, L = LS::L;
+    auto term = [&](float val, double n) {
+        const float p = fmaxf(val * (1.0f / D), 0x1.0p-126f);
+        part = __builtin_fma(n, static_cast<double>(__builtin_amdgcn_logf(p)), part);
+    };
+    const int tl = lane & (L - 1);
+    if constexpr (LS::kPasses > 0) {
+        uint16_t mu_next[V];
+        {
+            const int u = lane < LS::kTasks ? lane : 0;
+#pragma unroll
+            for (int j = 0; j < V; ++j) mu_next[j] = muv[u * V + j];
         }
-        float val = pauli[mu];
+#pragma unroll 1
+        for (int e = 0; e < LS::kPasses; ++e) {
+            const int u = lane + G * e;
+            const bool valid = LS::kPasses * G <= LS::kTasks || u < LS::kTasks;
+            const int uc = valid ? u : 0;
+            double n[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) n[j] = ndv[uc * V + j];
+            float v[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[j] = pauli[mu_next[j]];
+            if (e + 1 < LS::kPasses) {
+                const int un = u + G < LS::kTasks ? u + G : 0;
+#pragma unroll
+                for (int j = 0; j < V; ++j) mu_next[j] = muv[un * V + j];
+            }
+#pragma unroll
+            for (int s = 0; s < LS::kLogL; ++s) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const float other = xor_lane_stage_f32(v[j], s);
+                    v[j] = flip_sign(v[j], ((tl >> s) & 1u) << 31) + other;
+                }
+            }
+            wht_in_lane<V>(v);
+#pragma unroll
+            for (int j = 0; j < V; ++j) term(v[j], valid ? n[j] : 0.0);
+        }
+    }
+    if constexpr (LS::kRemFlat) {
+        const int i = lane & (D - 1);
+        const bool valid = lane < (LS::K - LS::kFlat0) * D;
+        const int f = valid ? LS::kFlat0 * D + lane : 0;
+        const double n = nd[f];
+        float val = pauli[mug[f]];
 #pragma unroll
         for (int s = 0; s < Q; ++s) {
             const float other = xor_lane_stage_f32(val, s);
             val = flip_sign(val, ((i >> s) & 1u) << 31) + other;
         }
-        const float p = fmaxf(val * (1.0f / D), 0x1.0p-126f);
-        const double n = valid ? n_raw : 0.0;
-        part = __builtin_fma(n, static_cast<double>(__builtin_amdgcn_logf(p)), part);
+        term(val, valid ? n : 0.0);
     }
 }
 
@@ -939,14 +1045,14 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             stage_pauli_f32<Q, G>(rhoP, pauli32, lane);
             sync();
             double part = 0.0;
-            stage_loglik_f32<Q, G>(pauli32, A.nd, A.mu, tables, lane, part);
+            stage_loglik_f32<Q, G>(pauli32, A.nd, A.mu, A.ndv, A.muv, lane, part);
             return kLn2 * team_sum<G>(part, misc + 4, lane);
         } else {
             stage_pauli<Q, G>(rhoP, pauli, lane);
             sync();
             double part_e = 0.0, part_f = 0.0;
             int bad = 0;
-            stage_loglik<Q, G>(pauli, A.nd, A.mu, tables, lane, part_e, part_f, bad);
+            stage_loglik<Q, G>(pauli, A.nd, A.mu, A.ndv, A.muv, tables, lane, part_e, part_f, bad);
             return team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
         }
     };
@@ -1122,6 +1228,7 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainA
 // row-major), one team per matrix.
 template <int Q, int G, int WG, int PREC = kPrecF64>
 __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, const uint16_t* __restrict__ mug,
+                                               const double* __restrict__ ndv, const uint16_t* __restrict__ muv,
                                                const double* rho, int64_t n, double* ll_out)
 {
     using Dm = Dims<Q>;
@@ -1150,7 +1257,7 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
         stage_pauli_f32<Q, G>(rhoP, pauli32, lane);
         __syncthreads();
         double part = 0.0;
-        stage_loglik_f32<Q, G>(pauli32, nd, mug, tables, lane, part);
+        stage_loglik_f32<Q, G>(pauli32, nd, mug, ndv, muv, lane, part);
         const double tot = team_sum<G>(part, misc + 4, lane);
         if (live && lane == 0) ll_out[idx] = kLn2 * tot;
     } else {
@@ -1158,7 +1265,7 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
         __syncthreads();
         double part_e = 0.0, part_f = 0.0;
         int bad = 0;
-        stage_loglik<Q, G>(pauli, nd, mug, tables, lane, part_e, part_f, bad);
+        stage_loglik<Q, G>(pauli, nd, mug, ndv, muv, tables, lane, part_e, part_f, bad);
         const double ll = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
         if (live && lane == 0) ll_out[idx] = ll;
     }

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_da_exact(DaAr
     __syncthreads();
     double part_e = 0.0, part_f = 0.0;
     int bad = 0;
-    stage_loglik<Q, G>(pauli, A.nd, A.mu, tables, lane, part_e, part_f, bad);
+    stage_loglik<Q, G>(pauli, A.nd, A.mu, A.ndv, A.muv, tables, lane, part_e, part_f, bad);
     const double llp = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
     // teams without a survivor (the tail of the last workgroup) run along to
     // the barrier below but write nothing

@@ -240,8 +240,8 @@ void launch_loglik_dense_t(const double* nd, const void* mfrag, const double* rh
 }
 
 template <int Q, int G, int WG, int PREC>
-void launch_loglik_t(const double* nd, const uint16_t* mu, const double* rho, int64_t n, double* out,
-                     hipStream_t s)
+void launch_loglik_t(const double* nd, const uint16_t* mu, const double* ndv, const uint16_t* muv, const double* rho,
+                     int64_t n, double* out, hipStream_t s)
 {
     using S = qst::TeamShape<Q, G>;
     const int64_t teams = WG / G;
@@ -250,7 +250,7 @@ void launch_loglik_t(const double* nd, const uint16_t* mu, const double* rho, in
     allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_loglik<Q, G, WG, PREC>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many states for one launch");
     hipLaunchKernelGGL((qst::k_loglik<Q, G, WG, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s, nd,
-                       mu, rho, n, out);
+                       mu, ndv, muv, rho, n, out);
     hip_check(hipGetLastError(), "loglik kernel launch");
 }
 
@@ -296,25 +296,27 @@ void launch_loglik_dense(int Q, int prec, const double* nd, const void* mfrag, c
 }
 
 template <int PREC>
-void launch_loglik_p(int Q, const double* nd, const uint16_t* mu, const double* rho, int64_t n, double* out,
+void launch_loglik_p(int Q, const double* nd, const uint16_t* mu, const double* ndv, const uint16_t* muv,
+                     const double* rho, int64_t n, double* out,
                      hipStream_t s)
 {
     switch (Q) {
-        case 1: return launch_loglik_t<1, 8, 64, PREC>(nd, mu, rho, n, out, s);
-        case 2: return launch_loglik_t<2, 16, 64, PREC>(nd, mu, rho, n, out, s);
-        case 3: return launch_loglik_t<3, 32, 64, PREC>(nd, mu, rho, n, out, s);
-        case 4: return launch_loglik_t<4, 64, 64, PREC>(nd, mu, rho, n, out, s);
-        case 5: return launch_loglik_t<5, 64, 64, PREC>(nd, mu, rho, n, out, s);
-        case 6: return launch_loglik_t<6, 256, 256, PREC>(nd, mu, rho, n, out, s);
+        case 1: return launch_loglik_t<1, 8, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
+        case 2: return launch_loglik_t<2, 16, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
+        case 3: return launch_loglik_t<3, 32, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
+        case 4: return launch_loglik_t<4, 64, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
+        case 5: return launch_loglik_t<5, 64, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
+        case 6: return launch_loglik_t<6, 256, 256, PREC>(nd, mu, ndv, muv, rho, n, out, s);
     }
     fail(QST_ERR_INVALID, "bad Q");
 }
 
-void launch_loglik(int Q, int prec, const double* nd, const uint16_t* mu, const double* rho, int64_t n, double* out,
+void launch_loglik(int Q, int prec, const double* nd, const uint16_t* mu, const double* ndv, const uint16_t* muv,
+                   const double* rho, int64_t n, double* out,
                    hipStream_t s)
 {
-    if (prec == qst::kPrecF32) return launch_loglik_p<qst::kPrecF32>(Q, nd, mu, rho, n, out, s);
-    return launch_loglik_p<qst::kPrecF64>(Q, nd, mu, rho, n, out, s);
+    if (prec == qst::kPrecF32) return launch_loglik_p<qst::kPrecF32>(Q, nd, mu, ndv, muv, rho, n, out, s);
+    return launch_loglik_p<qst::kPrecF64>(Q, nd, mu, ndv, muv, rho, n, out, s);
 }
 
 struct DeviceGuard {
@@ -336,6 +338,8 @@ struct qst_problem {
     std::vector<int64_t> counts;
     double* nd = nullptr;  // counts as doubles
     uint16_t* mu = nullptr;  // Pauli index of every (setting, transform position), [KD]
+    double* ndv = nullptr;   // counts in the task-major order of the likelihood transforms, [KD]
+    uint16_t* muv = nullptr; // Pauli indices in the same order, [KD]
     void* mfrag[3] = {nullptr, nullptr, nullptr};  // dense path: Pauli matrix fragments per precision
 
     const void* fragments(int prec)
@@ -523,6 +527,26 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
             }
         p->mu = dev_alloc<uint16_t>(p->KD);
         hip_check(hipMemcpy(p->mu, mu.data(), sizeof(uint16_t) * p->KD, hipMemcpyHostToDevice), "copy Pauli index");
+        // task-major copies: task u = k L + tl holds positions t = tl + L j,
+        // j < V, of setting k (V = min(4, D), L = D / V), entry u V + j
+        {
+            const int V = p->D < 4 ? p->D : 4, L = p->D / V;
+            std::vector<double> ndv(p->KD);
+            std::vector<uint16_t> muv(p->KD);
+            for (int k = 0; k < p->K; ++k)
+                for (int tl = 0; tl < L; ++tl)
+                    for (int j = 0; j < V; ++j) {
+                        const size_t src = static_cast<size_t>(k) * p->D + tl + L * j;
+                        const size_t dst = (static_cast<size_t>(k) * L + tl) * V + j;
+                        ndv[dst] = nd[src];
+                        muv[dst] = mu[src];
+                    }
+            p->ndv = dev_alloc<double>(p->KD);
+            p->muv = dev_alloc<uint16_t>(p->KD);
+            hip_check(hipMemcpy(p->ndv, ndv.data(), sizeof(double) * p->KD, hipMemcpyHostToDevice), "copy counts");
+            hip_check(hipMemcpy(p->muv, muv.data(), sizeof(uint16_t) * p->KD, hipMemcpyHostToDevice),
+                      "copy Pauli index");
+        }
         if (p->path == QST_PATH_DENSE) p->fragments(p->precision);
         *out = p.release();
     });
@@ -538,6 +562,8 @@ void qst_free_problem(qst_problem* p)
     p->free_state();
     dev_free(p->nd);
     dev_free(p->mu);
+    dev_free(p->ndv);
+    dev_free(p->muv);
     for (auto& f : p->mfrag) dev_free(f);
     (void)hipSetDevice(prev);
     delete p;
@@ -565,6 +591,8 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
     qst::ChainArgs a{};
     a.nd = p->nd;
     a.mu = p->mu;
+    a.ndv = p->ndv;
+    a.muv = p->muv;
     a.mfrag = p->path == QST_PATH_DENSE ? p->fragments(p->precision) : nullptr;
     a.R = p->R;
     a.x = p->x;
@@ -896,8 +924,8 @@ qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double
             const void* f = const_cast<qst_problem*>(p)->fragments(precision);
             launch_loglik_dense(p->Q, precision, p->nd, f, rho, n, ll_out, static_cast<hipStream_t>(stream));
         } else {
-            launch_loglik(p->Q, precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64, p->nd, p->mu, rho, n, ll_out,
-                          static_cast<hipStream_t>(stream));
+            launch_loglik(p->Q, precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64, p->nd, p->mu, p->ndv, p->muv,
+                          rho, n, ll_out, static_cast<hipStream_t>(stream));
         }
     });
 }
