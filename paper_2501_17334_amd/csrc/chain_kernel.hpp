@@ -458,6 +458,15 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
     }
 }
 
+// The same without the register copy: packed rho' stays in rhoP only, where
+// each lane finds its own slots p = packed_slot(lane, e) again.
+template <int Q, int G>
+__device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double* rhoP, int lane)
+{
+    double unused[TeamShape<Q, G>::NPL];
+    stage_rho<Q, G>(ybuf, wt, rhoP, unused, lane);
+}
+
 // Pauli coefficients c_mu = Tr(rho sigma_mu), mu = sum_q mu_q 4^(Q-1-q) with
 // mu_q in {I=0, X=1, Y=2, Z=3}.  sigma_mu has one non-zero per row:
 // (sigma_mu)_{a^m, a} = i^nY (-1)^popcount(a & zy), with m marking the X/Y
@@ -499,39 +508,107 @@ __device__ __forceinline__ float xor_lane_stage_f32(float v, int s)
     }
 }
 
+// In-register butterflies over the V values of a lane (position bits
+// log2 L and log2 L + 1): lower output a + b, upper a - b.
+template <int V, typename T>
+__device__ __forceinline__ void wht_in_lane(T (&v)[V])
+{
+    if constexpr (V >= 2) {
+#pragma unroll
+        for (int j = 0; j < V; j += 2) {
+            const T a = v[j], b = v[j + 1];
+            v[j] = a + b;
+            v[j + 1] = a - b;
+        }
+    }
+    if constexpr (V == 4) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const T a = v[j], b = v[j + 2];
+            v[j] = a + b;
+            v[j + 2] = a - b;
+        }
+    }
+}
+
+// Work split of the Pauli-coefficient transforms: a lane holds V positions
+// a = al + L j (j < V, L = D / V) of generalised diagonal m (task u = m L +
+// al), V = min(2, D^2 / G) so that the tasks still fill the team; the top
+// butterfly stage is then a register add.  (Four positions, with re and im
+// of each in registers, spilled more and ran slower at 4 qubits.)
+template <int Q, int G>
+struct PauliSplit {
+    static constexpr int D = 1 << Q, D2 = D * D;
+    static constexpr int kFill = D2 / G;
+    static constexpr int V = kFill >= 2 ? 2 : 1;
+    static constexpr int L = D / V;
+    static constexpr int kLogL = L == 1 ? 0 : L == 2 ? 1 : L == 4 ? 2 : L == 8 ? 3 : L == 16 ? 4 : 5;
+    static constexpr int kTasks = D * L;
+    static constexpr int kPasses = (kTasks + G - 1) / G;
+    static_assert(G % L == 0 || L % G == 0, "transform groups tile the team");
+};
+
+// The Pauli coefficients of packed rho' (Re rho_ab at (a, b) for a <= b,
+// Im rho_ba at (a, b) for a > b): for each generalised diagonal m, the
+// D-point Walsh-Hadamard transform of rho_{a, a^m} over a gives, at output z,
+// Tr(rho Z^z X^m) up to the phase i^{popcount(m & z)}.
+template <int Q, int G, typename T>
+__device__ __forceinline__ void stage_pauli_t(const double* rhoP, T* pauli, int lane)
+{
+    using PS = PauliSplit<Q, G>;
+    constexpr int D = PS::D, V = PS::V, L = PS::L;
+    const int al = lane & (L - 1);
+#pragma unroll 1
+    for (int e = 0; e < PS::kPasses; ++e) {
+        const int u = lane + G * e;          // u = m L + al
+        const bool valid = (PS::kPasses * G == PS::kTasks) || u < PS::kTasks;
+        const int m = valid ? (u / L) : 0;
+        T re[V], im[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int a = al + L * j;
+            const int b = a ^ m;
+            const int lo = a < b ? a : b, hi = a < b ? b : a;
+            re[j] = static_cast<T>(rhoP[lo * D + hi]);
+            const T pim = static_cast<T>(rhoP[hi * D + lo]);   // Im of the upper element (a != b)
+            im[j] = (a == b) ? T(0) : (a < b ? pim : -pim);
+        }
+#pragma unroll
+        for (int s = 0; s < PS::kLogL; ++s) {
+            // upper butterfly output other - own, lower own + other
+            const uint32_t sg = ((al >> s) & 1u) << 31;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                T ore, oim;
+                if constexpr (sizeof(T) == 8) {
+                    ore = xor_lane_stage<Q>(re[j], s);
+                    oim = xor_lane_stage<Q>(im[j], s);
+                } else {
+                    ore = xor_lane_stage_f32(re[j], s);
+                    oim = xor_lane_stage_f32(im[j], s);
+                }
+                re[j] = flip_sign(re[j], sg) + ore;
+                im[j] = flip_sign(im[j], sg) + oim;
+            }
+        }
+        wht_in_lane<V>(re);
+        wht_in_lane<V>(im);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int zy = al + L * j;
+            const int r4 = __popc(m & zy) & 3;
+            const T c = r4 == 0 ? re[j] : (r4 == 1 ? -im[j] : (r4 == 2 ? -re[j] : im[j]));
+            // digit (m_q, zy_q): (0,0) -> I, (1,0) -> X, (1,1) -> Y, (0,1) -> Z
+            const int mu = (spread_bits(zy) << 1) | spread_bits(m ^ zy);
+            if (valid) pauli[mu] = c;
+        }
+    }
+}
+
 template <int Q, int G>
 __device__ __forceinline__ void stage_pauli(const double* rhoP, double* pauli, int lane)
 {
-    using Dm = Dims<Q>;
-    constexpr int D = Dm::D, D2 = Dm::D2;
-    constexpr int NPASS = (D2 + G - 1) / G;
-    const int a = lane & (D - 1);
-#pragma unroll 1
-    for (int e = 0; e < NPASS; ++e) {
-        const int item = lane + G * e;          // item = m D + a
-        const bool valid = (NPASS * G == D2) || item < D2;
-        const int m = valid ? (item >> Q) : 0;
-        const int b = a ^ m;
-        const int lo = a < b ? a : b, hi = a < b ? b : a;
-        double re = rhoP[lo * D + hi];
-        const double pim = rhoP[hi * D + lo];   // Im of the upper element (a != b)
-        double im = (a == b) ? 0.0 : (a < b ? pim : -pim);
-#pragma unroll
-        for (int s = 0; s < Q; ++s) {
-            // upper butterfly output other - own, lower own + other
-            const uint32_t sg = ((a >> s) & 1u) << 31;
-            const double ore = xor_lane_stage<Q>(re, s);
-            const double oim = xor_lane_stage<Q>(im, s);
-            re = flip_sign(re, sg) + ore;
-            im = flip_sign(im, sg) + oim;
-        }
-        const int zy = a;
-        const int r4 = __popc(m & zy) & 3;
-        const double c = r4 == 0 ? re : (r4 == 1 ? -im : (r4 == 2 ? -re : im));
-        // digit (m_q, zy_q): (0,0) -> I, (1,0) -> X, (1,1) -> Y, (0,1) -> Z
-        const int mu = (spread_bits(zy) << 1) | spread_bits(m ^ zy);
-        if (valid) pauli[mu] = c;
-    }
+    stage_pauli_t<Q, G, double>(rhoP, pauli, lane);
 }
 
 // The same Pauli coefficients with the transform in FP32 (the mixed-precision
@@ -539,34 +616,7 @@ __device__ __forceinline__ void stage_pauli(const double* rhoP, double* pauli, i
 template <int Q, int G>
 __device__ __forceinline__ void stage_pauli_f32(const double* rhoP, float* pauli, int lane)
 {
-    using Dm = Dims<Q>;
-    constexpr int D = Dm::D, D2 = Dm::D2;
-    constexpr int NPASS = (D2 + G - 1) / G;
-    const int a = lane & (D - 1);
-#pragma unroll 1
-    for (int e = 0; e < NPASS; ++e) {
-        const int item = lane + G * e;
-        const bool valid = (NPASS * G == D2) || item < D2;
-        const int m = valid ? (item >> Q) : 0;
-        const int b = a ^ m;
-        const int lo = a < b ? a : b, hi = a < b ? b : a;
-        float re = static_cast<float>(rhoP[lo * D + hi]);
-        const float pim = static_cast<float>(rhoP[hi * D + lo]);
-        float im = (a == b) ? 0.0f : (a < b ? pim : -pim);
-#pragma unroll
-        for (int s = 0; s < Q; ++s) {
-            const uint32_t sg = ((a >> s) & 1u) << 31;
-            const float ore = xor_lane_stage_f32(re, s);
-            const float oim = xor_lane_stage_f32(im, s);
-            re = flip_sign(re, sg) + ore;
-            im = flip_sign(im, sg) + oim;
-        }
-        const int zy = a;
-        const int r4 = __popc(m & zy) & 3;
-        const float c = r4 == 0 ? re : (r4 == 1 ? -im : (r4 == 2 ? -re : im));
-        const int mu = (spread_bits(zy) << 1) | spread_bits(m ^ zy);
-        if (valid) pauli[mu] = c;
-    }
+    stage_pauli_t<Q, G, float>(rhoP, pauli, lane);
 }
 
 // Work split of the per-setting transforms.  A lane holds V = min(4, D)
@@ -592,29 +642,6 @@ struct LikSplit {
     static constexpr int kFlat0 = kWhole * (G / L);   // first setting of the one-value pass
     static_assert(G % L == 0, "a team holds whole settings");
 };
-
-// In-register butterflies over the V values of a lane (positions bits
-// kLogL, kLogL + 1): lower output a + b, upper a - b.
-template <int V, typename T>
-__device__ __forceinline__ void wht_in_lane(T (&v)[V])
-{
-    if constexpr (V >= 2) {
-#pragma unroll
-        for (int j = 0; j < V; j += 2) {
-            const T a = v[j], b = v[j + 1];
-            v[j] = a + b;
-            v[j + 1] = a - b;
-        }
-    }
-    if constexpr (V == 4) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const T a = v[j], b = v[j + 2];
-            v[j] = a + b;
-            v[j + 2] = a - b;
-        }
-    }
-}
 
 // Probabilities of every projector by a 2^Q-point Walsh-Hadamard transform
 // per setting, and this lane's share of sum c log p, kept as
@@ -938,7 +965,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
 
     // registers: state entries i = lane + G e, packed-rho entries p = lane + G e
     double y[S::NYL];
-    double rc[S::NPL], rp[S::NPL], s1[S::NPL], s2[S::NPL];
+    double rc[S::NPL], s1[S::NPL], s2[S::NPL];
     double ll, beta;
     int acc_w;
     int64_t nst, nacc = 0, nnear = 0;
@@ -1036,7 +1063,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     };
 
     auto evaluate = [&]() -> double {
-        stage_rho<Q, G>(ybuf, wt, rhoP, rp, lane);
+        stage_rho<Q, G>(ybuf, wt, rhoP, lane);
         sync();
         if constexpr (PATH == kPathDense) {
             return dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, PATH>::kOffRed, A.mfrag, A.nd, logtab, tid);
@@ -1069,7 +1096,8 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         }
 #pragma unroll
         for (int e = 0; e < S::NPL; ++e) {
-            rc[e] = rp[e];
+            const int p = packed_slot<Q, G>(lane, e);
+            rc[e] = p < D2 ? rhoP[p] : 0.0;
             s1[e] = 0.0;
             s2[e] = 0.0;
         }
@@ -1136,7 +1164,10 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
                 if (i < d) y[e] = ybuf[i];
             }
 #pragma unroll
-            for (int e = 0; e < S::NPL; ++e) rc[e] = rp[e];
+            for (int e = 0; e < S::NPL; ++e) {
+                const int p = packed_slot<Q, G>(lane, e);   // this lane's own writes in stage_rho
+                rc[e] = p < D2 ? rhoP[p] : 0.0;
+            }
             ll = llp;
             ++acc_w;
             ++nacc;
