@@ -39,7 +39,7 @@ class _RunDesc(C.Structure):
                 ("adapt_every", C.c_int32), ("adapt_lo", C.c_double), ("adapt_hi", C.c_double),
                 ("adapt_factor", C.c_double), ("adapt_until", C.c_int64), ("seed", C.c_uint64),
                 ("surrogate", C.POINTER(_Mlp)), ("trace_chains", C.c_int32),
-                ("record_every", C.c_int32), ("record_chains", C.c_int32)]
+                ("record_every", C.c_int32), ("record_chains", C.c_int32), ("param", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -67,6 +67,10 @@ def lib():
         L.orc_da_uniform.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
         L.orc_da_uniform.restype = C.c_double
         L.orc_rho.argtypes = [C.c_int, c_double_p, c_double_p]
+        L.orc_rho_bures.argtypes = [C.c_int, c_double_p, c_double_p]
+        L.orc_bures_unitary.argtypes = [C.c_int, c_double_p, c_double_p]
+        L.orc_param_dim.argtypes = [C.c_int, C.c_int]
+        L.orc_param_dim.restype = C.c_int
         L.orc_pack.argtypes = [C.c_int, c_double_p, c_double_p]
         L.orc_unpack.argtypes = [C.c_int, c_double_p, c_double_p]
         L.orc_probs.argtypes = [C.c_int, c_double_p, c_double_p]
@@ -94,9 +98,14 @@ def num_threads():
     return lib().orc_num_threads()
 
 
-def dims(Q):
+# parameterisations: the Gaussian/gamma form (2D^2+D parameters) and the
+# paper's Algorithm 1, the Bures draw (4D^2 parameters)
+PARAMS = {"gamma": 0, "bures": 1}
+
+
+def dims(Q, param="gamma"):
     D = 2 ** Q
-    return D, 3 ** Q, 2 * D * D + D
+    return D, 3 ** Q, (4 * D * D if param == "bures" else 2 * D * D + D)
 
 
 # --------------------------------------------------------------------------
@@ -129,13 +138,23 @@ def da_uniform(seed, chain, step):
     return lib().orc_da_uniform(seed, chain, step)
 
 
-def rho_of_x(Q, x):
-    """rho(x) as a D x D complex matrix."""
-    D, _, d = dims(Q)
+def rho_of_x(Q, x, param="gamma"):
+    """rho(x) as a D x D complex matrix (param "bures": Algorithm 1)."""
+    D, _, d = dims(Q, param)
     x = np.ascontiguousarray(x, dtype=np.float64)
     assert x.shape == (d,)
     out = np.zeros(2 * D * D)
-    lib().orc_rho(Q, _p(x), _p(out))
+    (lib().orc_rho_bures if param == "bures" else lib().orc_rho)(Q, _p(x), _p(out))
+    return out.reshape(D, D, 2) @ np.array([1.0, 1j])
+
+
+def bures_unitary(Q, x):
+    """U = Q Lambda of Algorithm 1 for the H part of x (D x D complex)."""
+    D, _, d = dims(Q, "bures")
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    assert x.shape == (d,)
+    out = np.zeros(2 * D * D)
+    lib().orc_bures_unitary(Q, _p(x), _p(out))
     return out.reshape(D, D, 2) @ np.array([1.0, 1j])
 
 
@@ -237,6 +256,7 @@ class RunParams:
     record_every: int = 0
     record_chains: int = 0
     surrogate: MlpWeights | None = None
+    param: str = "gamma"            # "bures": Algorithm 1 (4D^2 parameters)
 
 
 class Chains:
@@ -246,7 +266,7 @@ class Chains:
 
     def __init__(self, Q, counts, params: RunParams):
         self.Q = Q
-        self.D, self.K, self.d = dims(Q)
+        self.D, self.K, self.d = dims(Q, params.param)
         self.counts = np.ascontiguousarray(counts, dtype=np.int64).reshape(-1)
         assert self.counts.shape == (self.K * self.D,)
         self.p = params
@@ -270,7 +290,8 @@ class Chains:
         return _RunDesc(self.Q, _p(self.counts, c_int64_p), p.n_chains, p.chain_offset,
                         self.step, n_steps, p.thin, p.burn_in, p.beta0, p.adapt_every,
                         p.adapt_lo, p.adapt_hi, p.adapt_factor, p.adapt_until, p.seed,
-                        self._mlp, p.trace_chains, p.record_every, p.record_chains)
+                        self._mlp, p.trace_chains, p.record_every, p.record_chains,
+                        PARAMS[p.param])
 
     def _state(self, n_steps, bufs):
         R = self.p.n_chains

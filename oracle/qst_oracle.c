@@ -18,7 +18,9 @@
  *     of a complex Gaussian matrix and w_j = v_j^2 / sum_k v_k^2 (Dirichlet
  *     weights with concentration 1/2): the Gaussian/gamma-derived
  *     parameterisation that replaces the Bures draw of Algorithm 1, with the
- *     real/imaginary block order of Algorithm 1 (Steps 2-3).
+ *     real/imaginary block order of Algorithm 1 (Steps 2-3); and, as an
+ *     option, Algorithm 1 itself (the Bures draw: complex Householder QR of
+ *     a Gaussian H, the phase fix U = Q Lambda, W = (U + I) G).
  *   - p_kl = Tr(Lambda_kl rho) for all 3^Q Pauli settings and 2^Q outcomes
  *     (Section "Steps", step 1; all Pauli settings as in Section "Simulated
  *     Results"), evaluated as <e_kl| rho |e_kl> from the product vector e_kl.
@@ -173,6 +175,123 @@ void orc_rho(int Q, const double* x, double* rho_out)
     free(nz);
 }
 
+/* ----------------------------------------------------------------------- */
+/* The paper's own parameterisation, Algorithm 1 (Bures draw): x of length   */
+/* 4D^2, G = x[0:D^2] + i x[D^2:2D^2], H = x[2D^2:3D^2] + i x[3D^2:4D^2],     */
+/* both filled column by column (entry (i, j) at offset jD + i); H = QR;     */
+/* U = Q Lambda with Lambda = diag(r_kk / |r_kk|) (Mezzadri 2007), which is  */
+/* the unitary factor whose R has a positive real diagonal and so does not   */
+/* depend on the sign convention of the QR; W = (U + I) G; rho = W W^dag /   */
+/* Tr(W W^dag) (Al Osipov, Sommers & Zyczkowski 2010).                      */
+/* ----------------------------------------------------------------------- */
+int orc_param_dim(int Q, int param)
+{
+    const int D = 1 << Q, D2 = D * D;
+    return param == 1 ? 4 * D2 : 2 * D2 + D;
+}
+
+/* Householder QR of the D x D complex matrix A (row-major, overwritten by R
+ * in its upper triangle) with Q formed explicitly (row-major); textbook
+ * complex Householder reflections P_k = I - 2 v v^dag / (v^dag v) with
+ * v = x + e^{i arg x_0} |x| e_1, so that P_k x = -e^{i arg x_0} |x| e_1. */
+static void householder_qr(int D, double complex* A, double complex* Qm)
+{
+    double complex* V = calloc((size_t)D * D, sizeof(double complex));   /* v_k in column k, rows k.. */
+    double* vn = calloc((size_t)D, sizeof(double));
+    for (int k = 0; k < D; ++k) {
+        double alpha = 0.0;
+        for (int i = k; i < D; ++i) alpha += creal(A[i * D + k] * conj(A[i * D + k]));
+        alpha = sqrt(alpha);
+        if (alpha == 0.0) { vn[k] = 0.0; continue; }
+        const double complex x0 = A[k * D + k];
+        const double complex ph = cabs(x0) > 0.0 ? x0 / cabs(x0) : 1.0;
+        for (int i = k; i < D; ++i) V[i * D + k] = A[i * D + k];
+        V[k * D + k] += ph * alpha;
+        double nv = 0.0;
+        for (int i = k; i < D; ++i) nv += creal(V[i * D + k] * conj(V[i * D + k]));
+        vn[k] = nv;
+        for (int j = k; j < D; ++j) {
+            double complex s = 0.0;
+            for (int i = k; i < D; ++i) s += conj(V[i * D + k]) * A[i * D + j];
+            s *= 2.0 / nv;
+            for (int i = k; i < D; ++i) A[i * D + j] -= V[i * D + k] * s;
+        }
+    }
+    /* Q = P_0 P_1 ... P_{D-1}: apply the reflections to I, last one first */
+    for (int i = 0; i < D * D; ++i) Qm[i] = 0.0;
+    for (int i = 0; i < D; ++i) Qm[i * D + i] = 1.0;
+    for (int k = D - 1; k >= 0; --k) {
+        if (vn[k] == 0.0) continue;
+        for (int j = 0; j < D; ++j) {
+            double complex s = 0.0;
+            for (int i = k; i < D; ++i) s += conj(V[i * D + k]) * Qm[i * D + j];
+            s *= 2.0 / vn[k];
+            for (int i = k; i < D; ++i) Qm[i * D + j] -= V[i * D + k] * s;
+        }
+    }
+    free(V);
+    free(vn);
+}
+
+/* U = Q Lambda of Algorithm 1 for the H of x (D x D complex, row-major,
+ * interleaved (re, im)). */
+void orc_bures_unitary(int Q, const double* x, double* u_out)
+{
+    const int D = 1 << Q, D2 = D * D;
+    double complex* A = malloc(sizeof(double complex) * D2);
+    double complex* Qm = malloc(sizeof(double complex) * D2);
+    for (int j = 0; j < D; ++j)
+        for (int i = 0; i < D; ++i)
+            A[i * D + j] = x[2 * D2 + j * D + i] + I * x[3 * D2 + j * D + i];
+    householder_qr(D, A, Qm);
+    for (int i = 0; i < D; ++i)
+        for (int k = 0; k < D; ++k) {
+            const double complex r = A[k * D + k];
+            const double complex lam = cabs(r) > 0.0 ? r / cabs(r) : 1.0;
+            const double complex u = Qm[i * D + k] * lam;
+            u_out[2 * (i * D + k)] = creal(u);
+            u_out[2 * (i * D + k) + 1] = cimag(u);
+        }
+    free(A);
+    free(Qm);
+}
+
+/* rho(x) of Algorithm 1.  Output: D x D complex, row-major, interleaved. */
+void orc_rho_bures(int Q, const double* x, double* rho_out)
+{
+    const int D = 1 << Q, D2 = D * D;
+    double* u = malloc(sizeof(double) * 2 * D2);
+    double complex* Gm = malloc(sizeof(double complex) * D2);
+    double complex* W = malloc(sizeof(double complex) * D2);
+    orc_bures_unitary(Q, x, u);
+    for (int j = 0; j < D; ++j)
+        for (int i = 0; i < D; ++i) Gm[i * D + j] = x[j * D + i] + I * x[D2 + j * D + i];
+    /* W = (U + I) G */
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+            double complex acc = 0.0;
+            for (int m = 0; m < D; ++m) {
+                double complex um = u[2 * (a * D + m)] + I * u[2 * (a * D + m) + 1];
+                if (m == a) um += 1.0;
+                acc += um * Gm[m * D + b];
+            }
+            W[a * D + b] = acc;
+        }
+    double tr = 0.0;
+    for (int i = 0; i < D2; ++i) tr += creal(W[i] * conj(W[i]));
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+            double complex acc = 0.0;
+            for (int m = 0; m < D; ++m) acc += W[a * D + m] * conj(W[b * D + m]);
+            acc /= tr;
+            rho_out[2 * (a * D + b)] = creal(acc);
+            rho_out[2 * (a * D + b) + 1] = cimag(acc);
+        }
+    free(u);
+    free(Gm);
+    free(W);
+}
+
 /* Packed real form of a Hermitian matrix given as interleaved complex. */
 void orc_pack(int Q, const double* rho, double* packed)
 {
@@ -318,6 +437,7 @@ typedef struct {
     const orc_mlp* surrogate;   /* NULL = plain pCN */
     int32_t trace_chains;       /* first chains whose per-step values are traced */
     int32_t record_every, record_chains;
+    int32_t param;              /* 0: Gaussian/gamma form (2D^2+D); 1: Algorithm 1 (4D^2) */
 } orc_run_desc;
 
 /* Per-chain state; arrays are indexed by local chain index r in [0, n_chains). */
@@ -346,10 +466,11 @@ typedef struct {
 static int orc_K(int Q) { int K = 1; for (int q = 0; q < Q; ++q) K *= 3; return K; }
 
 /* Evaluate rho, packed rho and log L at x. */
-static double eval_state(int Q, const int64_t* counts, const double* x, double* rho,
+static double eval_state(int Q, int param, const int64_t* counts, const double* x, double* rho,
                          double* packed, double* p)
 {
-    orc_rho(Q, x, rho);
+    if (param == 1) orc_rho_bures(Q, x, rho);
+    else orc_rho(Q, x, rho);
     orc_pack(Q, rho, packed);
     orc_probs(Q, rho, p);
     return orc_loglik(Q, counts, p);
@@ -358,7 +479,7 @@ static double eval_state(int Q, const int64_t* counts, const double* x, double* 
 /* Initialise chains: Algorithm 2, line 1 (y^0 ~ N(0,I) from step 0's normals). */
 void orc_init_chains(const orc_run_desc* rd, orc_state* st)
 {
-    const int Q = rd->n_qubits, D = 1 << Q, D2 = D * D, d = 2 * D2 + D, K = orc_K(Q);
+    const int Q = rd->n_qubits, D = 1 << Q, D2 = D * D, d = orc_param_dim(Q, rd->param), K = orc_K(Q);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < rd->n_chains; ++r) {
         uint64_t chain = (uint64_t)(rd->chain_offset + r);
@@ -366,7 +487,7 @@ void orc_init_chains(const orc_run_desc* rd, orc_state* st)
         double* rho = malloc(sizeof(double) * 2 * D2);
         double* p = malloc(sizeof(double) * K * D);
         orc_normals(rd->seed, chain, 0, d, x);
-        st->ll[r] = eval_state(Q, rd->counts, x, rho, st->rho_cur + (size_t)r * D2, p);
+        st->ll[r] = eval_state(Q, rd->param, rd->counts, x, rho, st->rho_cur + (size_t)r * D2, p);
         st->beta[r] = rd->beta0;
         st->acc_win[r] = 0;
         memset(st->s1 + (size_t)r * D2, 0, sizeof(double) * D2);
@@ -381,7 +502,7 @@ void orc_init_chains(const orc_run_desc* rd, orc_state* st)
 /* Run steps step_begin+1 .. step_begin+n_steps of Algorithm 2 on every chain. */
 void orc_run_chains(const orc_run_desc* rd, orc_state* st)
 {
-    const int Q = rd->n_qubits, D = 1 << Q, D2 = D * D, d = 2 * D2 + D, K = orc_K(Q);
+    const int Q = rd->n_qubits, D = 1 << Q, D2 = D * D, d = orc_param_dim(Q, rd->param), K = orc_K(Q);
     const int64_t n_rec_per_chain = rd->record_every > 0 ? rd->n_steps / rd->record_every : 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < rd->n_chains; ++r) {
@@ -419,7 +540,7 @@ void orc_run_chains(const orc_run_desc* rd, orc_state* st)
                 const double logu1 = log(orc_da_uniform(rd->seed, chain, (uint64_t)j));
                 if (logu1 < s_prop - s_cur) {
                     ++n_s1;
-                    llp = eval_state(Q, rd->counts, yp, rho, packed, p);
+                    llp = eval_state(Q, rd->param, rd->counts, yp, rho, packed, p);
                     const double delta = (llp - ll) - (s_prop - s_cur);
                     accept = logu < delta;
                     if (fabs(logu - delta) < 1e-8) ++n_near;
@@ -428,7 +549,7 @@ void orc_run_chains(const orc_run_desc* rd, orc_state* st)
                 }
             } else {
                 /* line 5: rho(y') and L(y'); line 7: accept iff log alpha < dlogL */
-                llp = eval_state(Q, rd->counts, yp, rho, packed, p);
+                llp = eval_state(Q, rd->param, rd->counts, yp, rho, packed, p);
                 accept = logu < llp - ll;
                 if (fabs(logu - (llp - ll)) < 1e-8) ++n_near;
             }
@@ -514,7 +635,7 @@ void orc_eval_batch(int Q, const int64_t* counts, int64_t n, const double* xs,
         double* p = malloc(sizeof(double) * K * D);
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
-            ll_out[i] = eval_state(Q, counts, xs + (size_t)i * d, rho, packed, p);
+            ll_out[i] = eval_state(Q, 0, counts, xs + (size_t)i * d, rho, packed, p);
             if (packed_out) memcpy(packed_out + (size_t)i * D2, packed, sizeof(double) * D2);
         }
         free(rho);
