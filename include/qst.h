@@ -17,10 +17,12 @@
  * density matrices (the probability contraction on its own), qst_acf the
  * autocorrelation function Eq. (ACFrho) of recorded samples.
  *
- * Parameterisation (Gaussian/gamma-derived form of the Bures draw's
- * replacement): x in R^d, d = 2 D^2 + D, Re Z_ij = x[jD+i],
+ * Parameterisation (default; a Gaussian/gamma-derived replacement of the
+ * Bures draw): x in R^d, d = 2 D^2 + D, Re Z_ij = x[jD+i],
  * Im Z_ij = x[D^2+jD+i], v_j = x[2D^2+j]; w_j = v_j^2 / sum_k v_k^2 and
  * rho(x) = sum_j w_j z_j z_j^dag / (z_j^dag z_j), z_j the j-th column of Z.
+ * The paper's own Algorithm 1 (the Bures draw, d = 4 D^2) is selected with
+ * qst_problem_desc.param = QST_PARAM_BURES (see qst_param).
  *
  * Conventions: setting k = sum_q s_q 3^(Q-q), s in {X=0,Y=1,Z=2}; outcome
  * l = sum_q b_q 2^(Q-q), b = 0 the +1 eigenvalue; qubit 1 is the most
@@ -83,6 +85,21 @@ typedef enum {
                             FP32 (QST_ERR_UNSUPPORTED for QST_BF16X3) */
 } qst_path;
 
+/* The map x -> rho(x) (Section "Steps", step 2).  The prior is N(0, I) on x
+ * in both; the state x of qst_chain_state has d entries. */
+typedef enum {
+    QST_PARAM_GAMMA = 0,  /* the Gaussian/gamma-derived form above, d = 2 D^2 + D */
+    QST_PARAM_BURES = 1   /* Algorithm 1, the Bures draw, d = 4 D^2: G = x[0:D^2] +
+                             i x[D^2:2D^2], H = x[2D^2:3D^2] + i x[3D^2:4D^2], both
+                             filled column by column (entry (i,j) at offset jD+i);
+                             U = Q Lambda for H = QR with Lambda = diag(r_kk/|r_kk|)
+                             (the unitary whose triangular factor has a positive
+                             real diagonal; computed by Gram-Schmidt), W = (U + I) G,
+                             rho = W W^dag / Tr(W W^dag).  Kronecker path only
+                             (FP64 or FP32), 1..4 qubits, single-problem runs
+                             without a surrogate (QST_ERR_UNSUPPORTED otherwise) */
+} qst_param;
+
 typedef struct qst_problem qst_problem;   /* opaque; owns every device buffer behind it */
 
 typedef struct {
@@ -91,6 +108,7 @@ typedef struct {
     qst_precision precision;
     qst_path path;
     int32_t device;          /* HIP device ordinal the handle lives on */
+    qst_param param;         /* parameterisation; QST_PARAM_GAMMA when zero-initialised */
 } qst_problem_desc;
 
 /* Frozen MLP surrogate s(x) of log L for delayed acceptance (Christen & Fox

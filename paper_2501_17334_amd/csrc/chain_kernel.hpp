@@ -98,6 +98,16 @@ struct ChainArgs {
 
 // How p = Tr(Lambda rho) is formed inside the chain step.
 enum : int { kPathKron = 0, kPathDense = 1 };
+// Parameterisation rho(x): the Gaussian/gamma form (d = 2D^2 + D) or the
+// paper's Algorithm 1, the Bures draw (d = 4D^2).
+enum : int { kParamGamma = 0, kParamBures = 1 };
+
+template <int Q, int PARAM>
+struct ParamDims {
+    static constexpr int D = 1 << Q, D2 = D * D;
+    static constexpr int d = PARAM == kParamBures ? 4 * D2 : 2 * D2 + D;
+    static constexpr int NB = (d + 3) / 4;   // Philox blocks of normals per step
+};
 // Arithmetic of the dense contraction (the log-likelihood sum is FP64 always).
 enum : int { kPrecF64 = 0, kPrecF32 = 1, kPrecBF16x3 = 2 };
 
@@ -118,21 +128,25 @@ struct DenseShape {
     static constexpr int kStageDoubles = (6 * KP32 + 7) / 8;
 };
 
-template <int Q, int G, int PATH = kPathKron>
+template <int Q, int G, int PATH = kPathKron, int PARAM = kParamGamma>
 struct TeamShape {
     using Dm = Dims<Q>;
     static_assert(G >= Dm::D, "a team must hold one D-lane transform group");
     static_assert(G <= 64 ? (64 % G == 0) : (G % 64 == 0), "team size must tile wavefronts");
-    static constexpr int NJL = (Dm::NB + 1 + G - 1) / G;  // Philox jobs per lane (normals + MH uniform)
-    static constexpr int NYL = (Dm::d + G - 1) / G;       // state entries per lane (strided)
+    static constexpr int d = ParamDims<Q, PARAM>::d;     // parameters of rho(x)
+    static constexpr int NB = ParamDims<Q, PARAM>::NB;   // Philox blocks of normals per step
+    static constexpr int NJL = (NB + 1 + G - 1) / G;      // Philox jobs per lane (normals + MH uniform)
+    static constexpr int NYL = (d + G - 1) / G;           // state entries per lane (strided)
     static constexpr int NPL = (Dm::D2 + G - 1) / G;      // packed rho entries per lane (strided)
     static constexpr int NFL = (Dm::KD + G - 1) / G;      // projector outputs per lane
     static constexpr int kMisc = 24;                      // per-team scratch doubles
     // the Pauli-coefficient region doubles as the dense path's B-operand staging
     static constexpr int kPauliDoubles =
         PATH == kPathDense && DenseShape<Q>::kStageDoubles > Dm::D2 ? DenseShape<Q>::kStageDoubles : Dm::D2;
-    // per-team LDS (doubles): y' | Pauli coefficients | packed rho' | column weights | scratch
-    static constexpr int kOffPauli = Dm::d;
+    // per-team LDS (doubles): y' | Pauli coefficients | packed rho' | column weights | scratch.
+    // Algorithm 1 uses the Pauli and rho' regions (2 D^2 doubles) as its QR
+    // and product workspace before rho' is formed.
+    static constexpr int kOffPauli = d;
     static constexpr int kOffRho = kOffPauli + kPauliDoubles;
     static constexpr int kOffWt = kOffRho + Dm::D2;
     static constexpr int kOffMisc = kOffWt + Dm::D;
@@ -146,7 +160,7 @@ struct TeamShape {
     // that a step does not pay a whole pass for a few lanes (kRing = 1: no
     // ring).  kRing is capped so that the ring does not lower the number of
     // workgroups per CU of the tuned launch shape (LDS is the limit there).
-    static constexpr int kJobs = Dm::NB + 1;
+    static constexpr int kJobs = NB + 1;
     static constexpr int kFullJobs = kJobs / G * G;
     static constexpr int kTail = kJobs - kFullJobs;
     static constexpr int kRingCap = Q == 1 ? 2 : Q == 2 ? 3 : Q == 3 ? 10 : Q == 4 ? 6 : Q == 5 ? 18 : 30;
@@ -465,6 +479,235 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
 {
     double unused[TeamShape<Q, G>::NPL];
     stage_rho<Q, G>(ybuf, wt, rhoP, unused, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 (the Bures draw): rho(x) = W W^dag / Tr(W W^dag), W = (U + I) G
+// ---------------------------------------------------------------------------
+// Sum over the lanes of one matrix column: lane = j + D g, g < G / D (xor
+// masks D, 2D, ..., G/2); every lane of the column gets the same bits.
+template <int M, int G>
+__device__ __forceinline__ double column_sum(double v)
+{
+    if constexpr (M < G) {
+        v += xor_lane<M>(v);
+        return column_sum<2 * M, G>(v);
+    } else {
+        return v;
+    }
+}
+
+// U = Q Lambda of H = QR with Lambda = diag(r_kk / |r_kk|), i.e. the unitary
+// factor whose triangular factor has a positive real diagonal: the one that
+// Gram-Schmidt orthonormalisation of H's columns produces, whatever sign
+// convention a Householder QR would take.  Modified Gram-Schmidt across the
+// team: lane j + D g holds rows g + NG r (NG = G / D) of column j; column k is
+// normalised by its own lanes and broadcast through LDS (two alternating
+// buffers of 2D doubles in ubuf), then every later column loses its
+// component along it.  On return the lane holds U's entries of its rows.
+template <int Q, int G>
+struct BuresLayout {
+    static constexpr int D = 1 << Q, NG = G / D, RPL = (D + NG - 1) / NG;
+};
+
+template <int Q, int G>
+__device__ __forceinline__ void bures_unitary(const double* hbuf, double* ubuf, double (&ar)[BuresLayout<Q, G>::RPL],
+                                              double (&ai)[BuresLayout<Q, G>::RPL], int lane)
+{
+    using BL = BuresLayout<Q, G>;
+    constexpr int D = BL::D, D2 = D * D, NG = BL::NG, RPL = BL::RPL;
+    const int j = lane % D, g = lane / D;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = g + NG * r;
+        ar[r] = i < D ? hbuf[j * D + i] : 0.0;
+        ai[r] = i < D ? hbuf[D2 + j * D + i] : 0.0;
+    }
+#pragma unroll 1
+    for (int k = 0; k < D; ++k) {
+        double* ub = ubuf + (k & 1) * 2 * D;
+        // every lane takes part in the column sums (lane exchanges run with
+        // the whole wavefront active); only column k's lanes use this one
+        double n2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) n2 += ar[r] * ar[r] + ai[r] * ai[r];
+        n2 = column_sum<D, G>(n2);
+        if (j == k) {
+            const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = g + NG * r;
+                ar[r] *= inv;
+                ai[r] *= inv;
+                if (i < D) {
+                    ub[i] = ar[r];
+                    ub[D + i] = ai[r];
+                }
+            }
+        }
+        team_sync<G>();   // with two buffers, one wait per column suffices
+        // c = u_k^dag a_j, then a_j -= c u_k for the columns j > k
+        double ur[RPL], ui[RPL];
+        double cr = 0.0, ci = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = g + NG * r;
+            ur[r] = i < D ? ub[i] : 0.0;
+            ui[r] = i < D ? ub[D + i] : 0.0;
+            cr = __builtin_fma(ur[r], ar[r], __builtin_fma(ui[r], ai[r], cr));
+            ci = __builtin_fma(ur[r], ai[r], __builtin_fma(-ui[r], ar[r], ci));
+        }
+        cr = column_sum<D, G>(cr);
+        ci = column_sum<D, G>(ci);
+        if (j > k) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                ar[r] -= cr * ur[r] - ci * ui[r];
+                ai[r] -= cr * ui[r] + ci * ur[r];
+            }
+        }
+    }
+}
+
+// rho(x) of Algorithm 1 into rhoP (packed).  ws: the team's 2 D^2 doubles of
+// workspace (the Pauli and rho' regions, which the later stages overwrite);
+// matrices in ws are stored column by column, entry (a, b) at b D + a (real
+// parts) and D^2 + b D + a (imaginary parts), the layout of x.
+template <int Q, int G>
+__device__ __forceinline__ void stage_rho_bures(const double* ybuf, double* ws, double* rhoP, double* misc, int lane)
+{
+    using BL = BuresLayout<Q, G>;
+    using S = TeamShape<Q, G>;
+    constexpr int D = BL::D, D2 = D * D, NG = BL::NG, RPL = BL::RPL;
+    const double* gbuf = ybuf;            // G: x[0 : 2D^2]
+    const double* hbuf = ybuf + 2 * D2;   // H: x[2D^2 : 4D^2]
+    double ar[RPL], ai[RPL];
+    bures_unitary<Q, G>(hbuf, ws, ar, ai, lane);
+    team_sync<G>();
+    {
+        const int j = lane % D, g = lane / D;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = g + NG * r;
+            if (i < D) {
+                ws[j * D + i] = ar[r] + (i == j ? 1.0 : 0.0);   // U + I
+                ws[D2 + j * D + i] = ai[r];
+            }
+        }
+    }
+    team_sync<G>();
+    double tpart = 0.0;
+    if constexpr (Q == 4 && G == 64) {
+        // W = (U + I) G on MFMA: Re W = Ar Gr - Ai Gi, Im W = Ar Gi + Ai Gr with
+        // K = 16 in four k-steps; operand lane l carries A[l % 16][4 ks + l / 16]
+        // and B[4 ks + l / 16][l % 16]; result register e of lane l is entry
+        // (l / 16 + 4 e, l % 16).
+        typedef double double4_t __attribute__((ext_vector_type(4)));
+        const int i = lane & 15, kq = lane >> 4;
+        double4_t wr = {0.0, 0.0, 0.0, 0.0}, wi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kk = 4 * ks + kq;
+            const double a_r = ws[kk * D + i], a_i = ws[D2 + kk * D + i];
+            const double b_r = gbuf[i * D + kk], b_i = gbuf[D2 + i * D + kk];
+            wr = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, b_r, wr, 0, 0, 0);
+            wr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i, b_i, wr, 0, 0, 0);
+            wi = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, b_i, wi, 0, 0, 0);
+            wi = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, b_r, wi, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tpart = __builtin_fma(wr[e], wr[e], __builtin_fma(wi[e], wi[e], tpart));
+        team_sync<G>();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int a = kq + 4 * e, b = i;
+            ws[b * D + a] = wr[e];
+            ws[D2 + b * D + a] = wi[e];
+        }
+    } else {
+        constexpr int NW = (D2 + G - 1) / G;
+        double wr[NW], wi[NW];
+#pragma unroll
+        for (int e = 0; e < NW; ++e) {
+            const int p = lane + G * e;
+            const int a = p % D, b = p / D;
+            double sr = 0.0, si = 0.0;
+            if (p < D2) {
+#pragma unroll 4
+                for (int m = 0; m < D; ++m) {
+                    const double u_r = ws[m * D + a], u_i = ws[D2 + m * D + a];
+                    const double g_r = gbuf[b * D + m], g_i = gbuf[D2 + b * D + m];
+                    sr = __builtin_fma(u_r, g_r, __builtin_fma(-u_i, g_i, sr));
+                    si = __builtin_fma(u_r, g_i, __builtin_fma(u_i, g_r, si));
+                }
+            }
+            wr[e] = sr;
+            wi[e] = si;
+            tpart = __builtin_fma(sr, sr, __builtin_fma(si, si, tpart));
+        }
+        team_sync<G>();
+#pragma unroll
+        for (int e = 0; e < NW; ++e) {
+            const int p = lane + G * e;
+            if (p < D2) {
+                ws[(p / D) * D + p % D] = wr[e];
+                ws[D2 + (p / D) * D + p % D] = wi[e];
+            }
+        }
+    }
+    const double inv_t = 1.0 / team_sum<G>(tpart, misc + 4, lane);   // 1 / Tr(W W^dag)
+    team_sync<G>();
+    // packed rho = Gram product of W's columns, scaled; the operands are read
+    // before any result is written, since rhoP lies inside ws
+    if constexpr (RhoLayout<Q, G>::kMfma) {
+        typedef double double4_t __attribute__((ext_vector_type(4)));
+        const int i = lane & 15, kq = lane >> 4;
+        double zr[4], zi[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j = 4 * t + kq;
+            zr[t] = ws[j * D + i];
+            zi[t] = ws[D2 + j * D + i];
+        }
+        double4_t re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zr[t], zr[t], re, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zi[t], re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zr[t], im, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f64_16x16x4f64(-zr[t], zi[t], im, 0, 0, 0);
+        }
+        team_sync<G>();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = kq + 4 * e, col = i;
+            rhoP[row * 16 + col] = (row <= col ? re[e] : -im[e]) * inv_t;
+        }
+    } else {
+        double acc[S::NPL];
+#pragma unroll
+        for (int e = 0; e < S::NPL; ++e) {
+            const int p = lane + G * e;
+            acc[e] = 0.0;
+            if (p < D2) {
+                const int a = p / D, b = p % D;
+                const int r = a <= b ? a : b, c = a <= b ? b : a;
+                const bool want_re = a <= b;
+#pragma unroll 4
+                for (int j = 0; j < D; ++j) {
+                    const double zr_r = ws[j * D + r], zi_r = ws[D2 + j * D + r];
+                    const double zr_c = ws[j * D + c], zi_c = ws[D2 + j * D + c];
+                    acc[e] += want_re ? zr_r * zr_c + zi_r * zi_c : zi_r * zr_c - zr_r * zi_c;
+                }
+            }
+        }
+        team_sync<G>();
+#pragma unroll
+        for (int e = 0; e < S::NPL; ++e) {
+            const int p = lane + G * e;
+            if (p < D2) rhoP[p] = acc[e] * inv_t;
+        }
+    }
 }
 
 // Pauli coefficients c_mu = Tr(rho sigma_mu), mu = sum_q mu_q 4^(Q-1-q) with
@@ -938,14 +1181,16 @@ __device__ __forceinline__ double dense_loglik_wg(double* lds_teams, double* red
 // ---------------------------------------------------------------------------
 // the chain tile
 // ---------------------------------------------------------------------------
-template <int Q, int G, int WG, int PATH, int PREC>
+template <int Q, int G, int WG, int PATH, int PREC, int PARAM = kParamGamma>
 __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tables, double* lds)
 {
     using Dm = Dims<Q>;
-    using S = TeamShape<Q, G, PATH>;
+    using S = TeamShape<Q, G, PATH, PARAM>;
+    static_assert(PARAM == kParamGamma || (PATH == kPathKron && Q <= 4 && G <= 64),
+                  "Algorithm 1 runs on the Kronecker path with one-wavefront teams");
     static_assert(PATH == kPathKron ? (PREC == kPrecF64 || PREC == kPrecF32) : (G == 64 && WG == 1024),
                   "unsupported path");
-    constexpr int D2 = Dm::D2, d = Dm::d, NB = Dm::NB;
+    constexpr int D2 = Dm::D2, d = S::d, NB = S::NB;
     static_assert(WG % G == 0, "workgroup must hold whole teams");
 
     const int tid = threadIdx.x;
@@ -1063,7 +1308,8 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     };
 
     auto evaluate = [&]() -> double {
-        stage_rho<Q, G>(ybuf, wt, rhoP, lane);
+        if constexpr (PARAM == kParamBures) stage_rho_bures<Q, G>(ybuf, pauli, rhoP, misc, lane);
+        else stage_rho<Q, G>(ybuf, wt, rhoP, lane);
         sync();
         if constexpr (PATH == kPathDense) {
             return dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, PATH>::kOffRed, A.mfrag, A.nd, logtab, tid);
@@ -1245,14 +1491,14 @@ constexpr int chain_min_waves()
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-template <int Q, int G, int WG, int PATH = kPathKron, int PREC = kPrecF64>
+template <int Q, int G, int WG, int PATH = kPathKron, int PREC = kPrecF64, int PARAM = kParamGamma>
 __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainArgs A)
 {
     extern __shared__ double lds[];
     wg_tables_init<Q, PATH>(lds, threadIdx.x, WG);
     __syncthreads();
-    chain_tile<Q, G, WG, PATH, PREC>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds,
-                                     lds + WgTables<Q, PATH>::kDoubles);
+    chain_tile<Q, G, WG, PATH, PREC, PARAM>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds,
+                                            lds + WgTables<Q, PATH>::kDoubles);
 }
 
 // Eq. (likelihood) for n given density matrices (complex, interleaved,

@@ -212,17 +212,17 @@ bool shape_compiled(int Q, Shape sh)
     return false;
 }
 
-template <int Q, int G, int WG, int PATH, int PREC>
+template <int Q, int G, int WG, int PATH, int PREC, int PARAM = qst::kParamGamma>
 void launch_chains_t(const qst::ChainArgs& a, hipStream_t s)
 {
-    using S = qst::TeamShape<Q, G, PATH>;
+    using S = qst::TeamShape<Q, G, PATH, PARAM>;
     const int64_t teams = WG / G;
     const int64_t blocks = (a.R + teams - 1) / teams;
     const size_t lds = (static_cast<size_t>(teams) * S::kLdsChain + qst::WgTables<Q, PATH>::kDoubles) * sizeof(double);
-    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC>), lds);
+    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC, PARAM>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many chains for one launch");
-    hipLaunchKernelGGL((qst::k_chains<Q, G, WG, PATH, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s,
-                       a);
+    hipLaunchKernelGGL((qst::k_chains<Q, G, WG, PATH, PREC, PARAM>), dim3(static_cast<unsigned>(blocks)), dim3(WG),
+                       lds, s, a);
     hip_check(hipGetLastError(), "chain kernel launch");
 }
 
@@ -252,6 +252,20 @@ void launch_loglik_t(const double* nd, const uint16_t* mu, const double* ndv, co
     hipLaunchKernelGGL((qst::k_loglik<Q, G, WG, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s, nd,
                        mu, ndv, muv, rho, n, out);
     hip_check(hipGetLastError(), "loglik kernel launch");
+}
+
+// Algorithm 1 (the Bures draw): the Kronecker route with one fixed team
+// shape per qubit count (one wavefront per chain at 4 qubits).
+void launch_chains_bures(int Q, int prec, const qst::ChainArgs& a, hipStream_t s)
+{
+    using namespace qst;
+#define QST_BURES(q, g, wg)                                                                             \
+    if (Q == q)                                                                                         \
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamBures>(a, s)     \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamBures>(a, s);
+    QST_BURES(1, 8, 64) QST_BURES(2, 16, 64) QST_BURES(3, 32, 64) QST_BURES(4, 64, 256)
+#undef QST_BURES
+    fail(QST_ERR_UNSUPPORTED, "Algorithm 1 (QST_PARAM_BURES) is built for 1..4 qubits");
 }
 
 void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a, hipStream_t s)
@@ -335,6 +349,7 @@ struct qst_problem {
     int Q = 0, D = 0, D2 = 0, d = 0, K = 0, KD = 0, device = 0;
     qst_precision precision = QST_FP64;
     qst_path path = QST_PATH_KRON;
+    qst_param param = QST_PARAM_GAMMA;
     std::vector<int64_t> counts;
     double* nd = nullptr;  // counts as doubles
     uint16_t* mu = nullptr;  // Pauli index of every (setting, transform position), [KD]
@@ -454,6 +469,8 @@ void validate_run(const qst_problem* p, const qst_run_desc& r)
     if (r.pair_every > 0 && r.pair_chains > 0 && (!r.pair_x || !r.pair_ll))
         fail(QST_ERR_INVALID, "pair buffers are NULL");
     if (r.pair_every > 0 && r.surrogate) fail(QST_ERR_UNSUPPORTED, "the pair recorder runs with plain pCN");
+    if (r.surrogate && p->param == QST_PARAM_BURES)
+        fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs with the Gaussian/gamma parameterisation");
     if (r.resume) {
         if (!p->have_run) fail(QST_ERR_STATE, "resume requested before any run of this handle");
         if (r.n_chains != p->R) fail(QST_ERR_INVALID, "resume with a different n_chains");
@@ -492,7 +509,10 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
         p->Q = Q;
         p->D = 1 << Q;
         p->D2 = p->D * p->D;
-        p->d = 2 * p->D2 + p->D;
+        if (desc->param != QST_PARAM_GAMMA && desc->param != QST_PARAM_BURES)
+            fail(QST_ERR_INVALID, "unknown parameterisation");
+        p->param = desc->param;
+        p->d = p->param == QST_PARAM_BURES ? 4 * p->D2 : 2 * p->D2 + p->D;
         p->K = ipow3(Q);
         p->KD = p->K * p->D;
         p->device = desc->device;
@@ -503,6 +523,8 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
             fail(QST_ERR_UNSUPPORTED, "the Kronecker path runs in FP64 or FP32; BF16x3 needs QST_PATH_DENSE");
         if (p->path == QST_PATH_DENSE && Q > 4)
             fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
+        if (p->param == QST_PARAM_BURES && (p->path != QST_PATH_KRON || Q > 4))
+            fail(QST_ERR_UNSUPPORTED, "Algorithm 1 (QST_PARAM_BURES) runs on the Kronecker path, 1..4 qubits");
         p->counts.assign(desc->counts, desc->counts + p->KD);
         std::vector<double> nd(p->KD);
         for (int i = 0; i < p->KD; ++i) {
@@ -766,6 +788,8 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
             for (int j = 0; j < i; ++j)
                 if (problems[j] == problems[i]) fail(QST_ERR_INVALID, "a handle appears twice in the batch");
             validate_run(problems[i], runs[i]);
+            if (n_problems > 1 && problems[i]->param == QST_PARAM_BURES)
+                fail(QST_ERR_UNSUPPORTED, "batches run the Gaussian/gamma parameterisation");
         }
         DeviceGuard g(dev);
         hipStream_t s = static_cast<hipStream_t>(runs[0].stream);
@@ -775,8 +799,11 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
         } else if (n_problems == 1) {
             qst_problem* p = problems[0];
             const qst::ChainArgs a = make_args(p, runs[0]);
-            launch_chains(p->Q, current_shape(p->Q), p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
-                          static_cast<int>(p->precision), a, s);
+            if (p->param == QST_PARAM_BURES)
+                launch_chains_bures(p->Q, static_cast<int>(p->precision), a, s);
+            else
+                launch_chains(p->Q, current_shape(p->Q), p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
+                              static_cast<int>(p->precision), a, s);
         } else {
             for (int i = 0; i < n_problems; ++i)
                 if (runs[i].surrogate) fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs one problem per call");

@@ -32,7 +32,12 @@ class QstError(RuntimeError):
 
 class _ProblemDesc(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("counts", C.POINTER(C.c_int64)),
-                ("precision", C.c_int), ("path", C.c_int), ("device", C.c_int32)]
+                ("precision", C.c_int), ("path", C.c_int), ("device", C.c_int32), ("param", C.c_int)]
+
+
+# parameterisation of rho(x): the Gaussian/gamma form (2D^2+D parameters) or
+# the paper's Algorithm 1, the Bures draw (4D^2 parameters)
+_PARAM = {"gamma": 0, "bures": 1}
 
 
 class _Surrogate(C.Structure):
@@ -164,16 +169,17 @@ class RunConfig:
 class Problem:
     """A tomography problem on one GPU (qst_init_problem / qst_free_problem)."""
 
-    def __init__(self, n_qubits, counts, precision="fp64", path="auto", device=0):
+    def __init__(self, n_qubits, counts, precision="fp64", path="auto", device=0, param="gamma"):
         self.Q = int(n_qubits)
         self.D = 2 ** self.Q
         self.K = 3 ** self.Q
-        self.d = 2 * self.D * self.D + self.D
+        self.param = param
+        self.d = 4 * self.D * self.D if param == "bures" else 2 * self.D * self.D + self.D
         self.counts = np.ascontiguousarray(counts, dtype=np.int64).reshape(-1)
         if self.counts.size != self.K * self.D:
             raise ValueError("counts must have 3^Q * 2^Q entries")
         desc = _ProblemDesc(self.Q, self.counts.ctypes.data_as(C.POINTER(C.c_int64)),
-                            _PREC[precision], _PATH[path], device)
+                            _PREC[precision], _PATH[path], device, _PARAM[param])
         h = C.c_void_p()
         _check(lib().qst_init_problem(C.byref(desc), C.byref(h)))
         self._h = h
@@ -192,7 +198,7 @@ class Problem:
 
     @property
     def pair_width(self):
-        """Width of a surrogate input row: 2D^2+D rounded up to a multiple of 32."""
+        """Width of a surrogate input row: d rounded up to a multiple of 32."""
         return (self.d + 31) // 32 * 32
 
     def _run_desc(self, cfg: RunConfig, trace=None, record=None, stream=None, surrogate=None, pairs=None):

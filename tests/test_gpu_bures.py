@@ -1,0 +1,148 @@
+"""The paper's Algorithm 1 (the Bures draw) on the GPU against the oracle.
+
+The GPU forms U by Gram-Schmidt across the team, the oracle by Householder
+reflections with the phase fix; both give the unitary whose triangular
+factor has a positive real diagonal, so they agree up to rounding, which
+the conditioning of H amplifies (the QR factors of H move by about
+cond(H) times the unit roundoff).  Hence:
+
+* chains traced against the oracle on 1..4 qubits: per-step log L within
+  1e-9 relative while the decisions agree (up to the first near-tie), final
+  states equal;
+* the packed rho of every chain's final state against the oracle's rho(x)
+  of that same state, within 1e-11;
+* the FP32 Kronecker form with Algorithm 1: per-step log L within the FP32
+  band of 2e-5 x total count;
+* 65536 chains on 4 qubits in the launch configuration of the benchmark:
+  the first two chains and the last one replayed by the oracle;
+* combinations that are not built are refused with QST_ERR_UNSUPPORTED.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2501_17334_amd import qst, synth
+from tests.gpu_util import first_near_step
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problem_for(Q):
+    return {1: synth.make_problem("c1"), 2: synth.make_problem("c2"), 3: synth.make_problem("w_3"),
+            4: synth.make_problem("c3")}[Q]
+
+
+def _run_pair(Q, counts, R, T, seed, beta0, precision="fp64", adapt_every=0, record=False):
+    P = qst.Problem(Q, counts, precision=precision, path="kron", param="bures")
+    D = 2 ** Q
+    tr = dict(chains=R, llprop=torch.full((R, T), float("nan"), dtype=torch.float64, device="cuda"),
+              logu=torch.zeros((R, T), dtype=torch.float64, device="cuda"),
+              accept=torch.zeros((R, T), dtype=torch.int8, device="cuda"))
+    rec = dict(every=T, chains=R, buf=torch.zeros((R, 1, D, D), dtype=torch.float64, device="cuda")) if record else None
+    P.run(qst.RunConfig(n_chains=R, n_steps=T, seed=seed, beta0=beta0, adapt_every=adapt_every), trace=tr,
+          record=rec)
+    torch.cuda.synchronize()
+    ch = O.Chains(Q, counts, O.RunParams(n_chains=R, n_steps=0, seed=seed, beta0=beta0, adapt_every=adapt_every,
+                                         trace_chains=R, param="bures"))
+    ll0 = ch.ll.copy()
+    o = ch.run(T)
+    g = {"llprop": tr["llprop"].cpu().numpy(), "accept": tr["accept"].cpu().numpy(),
+         "records": rec["buf"].cpu().numpy() if record else None}
+    return P, ch, o, ll0, g
+
+
+@pytest.mark.parametrize("Q", [1, 2, 3, 4])
+def test_bures_chains_match_oracle(Q):
+    prob = _problem_for(Q)
+    R, T, beta0 = {1: (24, 300, 0.1), 2: (24, 200, 0.05), 3: (16, 120, 0.03), 4: (8, 60, 0.02)}[Q]
+    print(f"[bures] Q={Q} R={R} T={T}", flush=True)
+    P, ch, o, ll0, g = _run_pair(Q, prob.counts, R, T, prob.seed, beta0, record=True)
+    stop = first_near_step(o["trace_llprop"], g["llprop"], o["trace_logu"], ll0, o["trace_accept"])
+    worst = 0.0
+    for r in range(R):
+        s = stop[r]
+        a, b = o["trace_llprop"][r, :s], g["llprop"][r, :s]
+        rel = np.abs(a - b) / np.abs(a)
+        worst = max(worst, float(rel.max()) if s else 0.0)
+        assert np.all(rel <= 1e-9), (r, rel.max())
+        assert np.array_equal(o["trace_accept"][r, :s], g["accept"][r, :s]), r
+    x, ll, _, _ = P.state()
+    assert x.shape == (R, 4 * 4 ** Q)
+    clean = stop == T
+    assert np.allclose(x[clean], ch.x[clean], rtol=1e-9, atol=1e-9)
+    # the packed rho the GPU holds for each final state against the oracle's rho(x)
+    D = 2 ** Q
+    for r in range(R):
+        want = O.pack(O.rho_of_x(Q, x[r], "bures"))
+        assert np.abs(g["records"][r, 0] - want).max() < 1e-11, r
+    print(f"  max relative |dlogL| {worst:.2e}; near-tie stops {int((~clean).sum())} of {R}", flush=True)
+
+
+def test_bures_fp32_form():
+    Q = 3
+    prob = _problem_for(Q)
+    R, T = 16, 100
+    P, ch, o, ll0, g = _run_pair(Q, prob.counts, R, T, prob.seed, 0.03, precision="fp32")
+    bar = 2e-5 * prob.counts.sum()
+    for r in range(R):
+        diff = np.nonzero(o["trace_accept"][r] != g["accept"][r])[0]
+        s = min((diff[0] if diff.size else T) + 1, T)
+        assert np.all(np.abs(o["trace_llprop"][r, :s] - g["llprop"][r, :s]) <= bar), r
+
+
+def test_bures_fullsize_sampled_chains():
+    """4 qubits, 65536 chains (the chain count of the benchmark workload) in
+    one launch; chains 0, 1 and the last one replayed by the oracle."""
+    prob = synth.make_problem("c3")
+    Q, R, T, beta = 4, 65536, 200, 0.0063
+    P = qst.Problem(Q, prob.counts, param="bures")
+    tr = dict(chains=2, llprop=torch.full((2, T), float("nan"), dtype=torch.float64, device="cuda"),
+              logu=torch.zeros((2, T), dtype=torch.float64, device="cuda"),
+              accept=torch.zeros((2, T), dtype=torch.int8, device="cuda"))
+    print(f"[bures fullsize] R={R} T={T}", flush=True)
+    st = P.run(qst.RunConfig(n_chains=R, n_steps=T, seed=prob.seed, beta0=beta, adapt_every=100), trace=tr)
+    torch.cuda.synchronize()
+    assert st["proposed"] == R * T
+    x, ll, _, _ = P.state()
+    ch = O.Chains(Q, prob.counts, O.RunParams(n_chains=2, n_steps=0, seed=prob.seed, beta0=beta, adapt_every=100,
+                                              trace_chains=2, param="bures"))
+    ll0 = ch.ll.copy()
+    o = ch.run(T)
+    g_ll = tr["llprop"].cpu().numpy()
+    stop = first_near_step(o["trace_llprop"], g_ll, o["trace_logu"], ll0, o["trace_accept"])
+    for r in range(2):
+        s = stop[r]
+        assert np.all(np.abs(o["trace_llprop"][r, :s] - g_ll[r, :s]) <= 1e-9 * np.abs(o["trace_llprop"][r, :s]))
+        if s == T:
+            assert np.allclose(x[r], ch.x[r], rtol=1e-9, atol=1e-9)
+    last = O.Chains(Q, prob.counts, O.RunParams(n_chains=1, n_steps=0, seed=prob.seed, beta0=beta, adapt_every=100,
+                                                chain_offset=R - 1, param="bures"))
+    last.run(T)
+    assert np.allclose(x[R - 1], last.x[0], rtol=1e-9, atol=1e-9)
+    assert abs(ll[R - 1] - last.ll[0]) <= 1e-9 * abs(last.ll[0])
+    pool = P.pool()
+    m = pool["mean"]
+    assert np.allclose(m, m.conj().T, atol=1e-14) and abs(np.trace(m).real - 1.0) < 1e-12
+    print(f"[bures fullsize] compared over {stop.tolist()} steps and the last chain", flush=True)
+
+
+def test_bures_unsupported_combinations():
+    p4 = synth.make_problem("c3")
+    with pytest.raises(qst.QstError):
+        qst.Problem(4, p4.counts, path="dense", param="bures")
+    p5 = synth.make_problem("c4")
+    with pytest.raises(qst.QstError):
+        qst.Problem(5, p5.counts, param="bures")
+    p2 = synth.make_problem("c2")
+    a = qst.Problem(2, p2.counts, param="bures")
+    b = qst.Problem(2, p2.counts)
+    cfg = qst.RunConfig(n_chains=8, n_steps=5, seed=1, beta0=0.1, adapt_every=0)
+    with pytest.raises(qst.QstError):
+        qst.run_batch([a, b], [cfg, cfg])
