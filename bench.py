@@ -40,6 +40,25 @@ def flops_per_chain_step(Q, stored_fraction):
     return proposal + weights + rho + contraction + loglik + moments
 
 
+def flops_per_chain_step_bures(Q, stored_fraction):
+    """Algorithmic FP64 flops of one chain-step with Algorithm 1 (the Bures
+    draw): the same contraction, likelihood and moments, with the proposal
+    over 4D^2 parameters and rho from Gram-Schmidt of H, W = (U + I) G and the
+    Gram product of W."""
+    D = 2 ** Q
+    d = 4 * D * D
+    KD = 6 ** Q
+    proposal = 2 * d
+    qr = 6 * D * D + 8 * D * D * (D - 1)   # column norms and scaling; c = u^dag a and a -= c u for j > k
+    w = 8 * D ** 3                         # (U + I) G, complex
+    trace = 4 * D * D
+    rho = 4 * D ** 3 + D * D               # Hermitian Gram product of W, scaled
+    contraction = sum(8 * 6 ** q * 4 ** (Q - q) for q in range(1, Q + 1))
+    loglik = 2 * KD
+    moments = 3 * D * D * stored_fraction
+    return proposal + qr + w + trace + rho + contraction + loglik + moments
+
+
 def kernel_source_hash():
     """Hash of the code the chain kernel is compiled from (its device code:
     the step, the random numbers, the fast math), comments and blank space
@@ -163,6 +182,41 @@ def chosen_forms(qst, torch, np, prob, cfg, record, plain_pool, plain_ms, plain_
                                     "chain_steps_per_s": R * dense_steps / (ms / 1e3), "ms": ms}
             P.close()
     return out
+
+
+def bures_form(qst, torch, np, prob, cfg, plain_pool):
+    """The paper's own parameterisation (Algorithm 1, the Bures draw) on the
+    same workload: its own pilot beta, the full run, its rate and the
+    achieved FP64 rate of its algorithmic flops, and the Frobenius distance
+    of its pooled mean to the true state next to the plain run's.  With
+    4D^2 parameters the pilot beta is about half the plain one and the
+    chains are still travelling towards the posterior after 10^4 steps, so
+    no ESS is reported for them."""
+    import dataclasses
+    Q, R, NT = prob.n_qubits, cfg.n_chains, cfg.n_steps
+    P = qst.Problem(Q, prob.counts, param="bures")
+    beta, pst = pilot_beta(qst, P, prob.seed)
+    c = dataclasses.replace(cfg, beta0=beta)
+    P.run(dataclasses.replace(c, n_chains=256, n_steps=10), stats=False)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    P.run(c, stats=False)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    pool = P.pool()
+    truth = prob.truth.density_matrix()
+    flop = flops_per_chain_step_bures(Q, (NT - cfg.burn_in) / NT)
+    tflops = flop * R * NT / (ms / 1e3) / 1e12
+    P.close()
+    return {"what": "Algorithm 1 (Bures draw, 4D^2 parameters): Gram-Schmidt U = Q Lambda, W = (U + I) G, "
+                    "rho = W W^dag / Tr, FP64, same workload and seeds, own pilot beta",
+            "beta0_from_pilot": beta, "pilot_acceptance": pst["accepted"] / pst["proposed"],
+            "chain_steps_per_s": R * NT / (ms / 1e3), "ms": ms,
+            "flop_per_chain_step": flop, "achieved_tflops": tflops, "frac_fp64_peak": tflops / PEAK_FP64_TFLOPS,
+            "mean_error_to_truth_frobenius": float(np.sqrt(np.sum(np.abs(pool["mean"] - truth) ** 2))),
+            "plain_mean_error_to_truth_frobenius": float(np.sqrt(np.sum(np.abs(plain_pool["mean"] - truth) ** 2)))}
 
 
 def delayed_acceptance(qst, surrogate, synth, torch, np, name="c4", warm=4000, pair_steps=2000, pair_every=20,
@@ -461,6 +515,8 @@ def main():
                 "between_chain_ess": ess_between,
                 "between_chain_ess_per_s": ess_between / (ms_step / 1e3)},
         "acceptance_note": "adaptation per Algorithm 2 (M_A=500) from the pilot beta",
+        "mean_error_to_truth_frobenius": float(np.sqrt(np.sum(np.abs(pool["mean"] - prob.truth.density_matrix())
+                                                               ** 2))),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": f"k_chains<Q={Q}>", "kernel_ms": ms_kernel,
@@ -469,6 +525,9 @@ def main():
     if not args.no_forms:
         print("[bench] chosen forms", file=sys.stderr, flush=True)
         out["forms"] = chosen_forms(qst, torch, np, prob, cfg, record, pool, ms_step, tau, ess_between)
+        if Q <= 4:
+            print("[bench] Algorithm 1 (Bures draw)", file=sys.stderr, flush=True)
+            out["forms"]["bures"] = bures_form(qst, torch, np, prob, cfg, pool)
         print("[bench] uneven batch", file=sys.stderr, flush=True)
         out["forms"]["uneven_batch"] = uneven_batch(qst, synth, torch, np)
         if not args.no_delayed:
