@@ -225,6 +225,14 @@ qst_status qst_pool_moments(const qst_problem* p, double* mean, double* second, 
 qst_status qst_chain_state(const qst_problem* p, double* x, double* loglik, double* beta,
                            int64_t* n_stored);
 
+/* Each chain's own moment sums of Eq. (BME2) to HOST buffers (NULL to
+ * skip): s1 [R][D*D] = sum of the packed rho of its stored samples, s2 the
+ * element-wise sum of squares (packed real form, see above); with n_stored
+ * of qst_chain_state, s1 / n_stored is chain r's estimate, and any subset of
+ * chains pools as sum s1 / sum n_stored (Eq. (BME2) for that subset).
+ * Waits for the last run. */
+qst_status qst_chain_moments(const qst_problem* p, double* s1, double* s2);
+
 /* Eq. (likelihood) for n density matrices: rho is a DEVICE array of n
  * complex D x D matrices (interleaved), ll_out a DEVICE array of n doubles.
  * path/precision as in qst_problem_desc (QST_PATH_AUTO: the handle's own).

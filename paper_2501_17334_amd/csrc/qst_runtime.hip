@@ -933,6 +933,19 @@ qst_status qst_chain_state(const qst_problem* p, double* x, double* loglik, doub
     });
 }
 
+qst_status qst_chain_moments(const qst_problem* p, double* s1, double* s2)
+{
+    return guarded([&] {
+        if (!p) fail(QST_ERR_INVALID, "NULL handle");
+        if (!p->have_run) fail(QST_ERR_STATE, "no chains yet");
+        DeviceGuard g(p->device);
+        if (p->last_stream) hip_check(hipStreamSynchronize(p->last_stream), "moments synchronize");
+        const size_t n = static_cast<size_t>(p->R) * p->D2;
+        if (s1) hip_check(hipMemcpy(s1, p->s1, sizeof(double) * n, hipMemcpyDeviceToHost), "moments copy");
+        if (s2) hip_check(hipMemcpy(s2, p->s2, sizeof(double) * n, hipMemcpyDeviceToHost), "moments copy");
+    });
+}
+
 qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double* ll_out, qst_path path,
                       qst_precision precision, void* stream)
 {

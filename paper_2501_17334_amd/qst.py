@@ -85,6 +85,7 @@ def lib():
                                        C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.qst_chain_state.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.qst_chain_moments.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.qst_loglik.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_int, vp]
         L.qst_acf.argtypes = [vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
         L.qst_set_launch_shape.argtypes = [C.c_int32, C.c_int32, C.c_int32]
@@ -108,7 +109,7 @@ def lib():
         L.qst_free_problem.restype = None
         L.qst_last_error.restype = C.c_char_p
         L.qst_version.restype = C.c_char_p
-        for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state",
+        for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state", "qst_chain_moments",
                   "qst_loglik", "qst_acf", "qst_set_launch_shape", "qst_get_launch_shape",
                   "qst_list_launch_shapes", "qst_mlp_create", "qst_mlp_set_params", "qst_mlp_get_params",
                   "qst_mlp_gradients", "qst_mlp_train_step", "qst_mlp_predict", "qst_mlp_surrogate",
@@ -258,6 +259,15 @@ class Problem:
         _check(lib().qst_chain_state(self._h, _f64(x), _f64(ll), _f64(beta),
                                      nst.ctypes.data_as(C.POINTER(C.c_int64))))
         return x, ll, beta, nst
+
+    def moments(self):
+        """qst_chain_moments: per-chain sums (s1 [R, D, D], s2 [R, D, D]) of the
+        packed rho of the stored samples."""
+        R, D = self.n_chains, self.D
+        s1 = np.zeros((R, D, D))
+        s2 = np.zeros((R, D, D))
+        _check(lib().qst_chain_moments(self._h, _f64(s1), _f64(s2)))
+        return s1, s2
 
     def loglik(self, rho_dev, out_dev, path="auto", precision="fp64", stream=None):
         """qst_loglik on torch device tensors: rho [n, D, D] complex128 (or
