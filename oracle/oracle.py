@@ -39,7 +39,8 @@ class _RunDesc(C.Structure):
                 ("adapt_every", C.c_int32), ("adapt_lo", C.c_double), ("adapt_hi", C.c_double),
                 ("adapt_factor", C.c_double), ("adapt_until", C.c_int64), ("seed", C.c_uint64),
                 ("surrogate", C.POINTER(_Mlp)), ("trace_chains", C.c_int32),
-                ("record_every", C.c_int32), ("record_chains", C.c_int32), ("param", C.c_int32)]
+                ("record_every", C.c_int32), ("record_chains", C.c_int32), ("param", C.c_int32),
+                ("povm", c_double_p), ("n_povm", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -74,6 +75,7 @@ def lib():
         L.orc_pack.argtypes = [C.c_int, c_double_p, c_double_p]
         L.orc_unpack.argtypes = [C.c_int, c_double_p, c_double_p]
         L.orc_probs.argtypes = [C.c_int, c_double_p, c_double_p]
+        L.orc_probs_povm.argtypes = [C.c_int, c_double_p, C.c_int, c_double_p, c_double_p]
         L.orc_loglik.argtypes = [C.c_int, c_int64_p, c_double_p]
         L.orc_loglik.restype = C.c_double
         L.orc_mlp_forward.argtypes = [C.POINTER(_Mlp), c_double_p]
@@ -186,6 +188,21 @@ def probs(Q, rho):
     return out.reshape(K, D)
 
 
+def _interleave(a):
+    a = np.asarray(a, dtype=complex)
+    return np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1).reshape(-1))
+
+
+def probs_povm(Q, rho, povm):
+    """p_m = Tr(Pi_m rho) for the POVM elements povm [n, D, D] (returns n values)."""
+    D, K, _ = dims(Q)
+    povm = np.asarray(povm, dtype=complex)
+    n = povm.shape[0]
+    out = np.zeros(K * D)
+    lib().orc_probs_povm(Q, _p(_interleave(rho)), n, _p(_interleave(povm)), _p(out))
+    return out[:n]
+
+
 def loglik(Q, counts, p):
     c = np.ascontiguousarray(counts, dtype=np.int64).reshape(-1)
     pp = np.ascontiguousarray(p, dtype=np.float64).reshape(-1)
@@ -257,6 +274,7 @@ class RunParams:
     record_chains: int = 0
     surrogate: MlpWeights | None = None
     param: str = "gamma"            # "bures": Algorithm 1 (4D^2 parameters)
+    povm: np.ndarray | None = None  # [n, D, D] POVM elements (counts then has n entries)
 
 
 class Chains:
@@ -268,6 +286,12 @@ class Chains:
         self.Q = Q
         self.D, self.K, self.d = dims(Q, params.param)
         self.counts = np.ascontiguousarray(counts, dtype=np.int64).reshape(-1)
+        self._povm = None
+        if params.povm is not None:
+            n = params.povm.shape[0]
+            assert self.counts.shape == (n,) and n <= self.K * self.D
+            self._povm = _interleave(params.povm)
+            self.counts = np.concatenate([self.counts, np.zeros(self.K * self.D - n, dtype=np.int64)])
         assert self.counts.shape == (self.K * self.D,)
         self.p = params
         R, D2 = params.n_chains, self.D * self.D
@@ -291,7 +315,8 @@ class Chains:
                         self.step, n_steps, p.thin, p.burn_in, p.beta0, p.adapt_every,
                         p.adapt_lo, p.adapt_hi, p.adapt_factor, p.adapt_until, p.seed,
                         self._mlp, p.trace_chains, p.record_every, p.record_chains,
-                        PARAMS[p.param])
+                        PARAMS[p.param], _p(self._povm),
+                        0 if p.povm is None else int(p.povm.shape[0]))
 
     def _state(self, n_steps, bufs):
         R = self.p.n_chains

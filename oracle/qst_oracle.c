@@ -368,6 +368,30 @@ void orc_probs(int Q, const double* rho, double* p)
 }
 
 /* log L = sum_{c>0} c log p; -inf if some p <= 0 carries a count. */
+/* p_m = Tr(Pi_m rho) for n given POVM elements (n complex D x D matrices,
+ * row-major, interleaved), written to p[0..n); p[n..3^Q 2^Q) = 0 (padding
+ * elements, which carry no counts). */
+void orc_probs_povm(int Q, const double* rho, int n, const double* povm, double* p)
+{
+    const int D = 1 << Q, D2 = D * D;
+    int K = 1;
+    for (int q = 0; q < Q; ++q) K *= 3;
+    for (int m = 0; m < K * D; ++m) {
+        double acc = 0.0;
+        if (m < n) {
+            const double* P = povm + (size_t)m * 2 * D2;
+            for (int a = 0; a < D; ++a)
+                for (int b = 0; b < D; ++b) {
+                    /* Re(Pi_ab rho_ba) */
+                    const double pr = P[2 * (a * D + b)], pi = P[2 * (a * D + b) + 1];
+                    const double rr = rho[2 * (b * D + a)], ri = rho[2 * (b * D + a) + 1];
+                    acc += pr * rr - pi * ri;
+                }
+        }
+        p[m] = acc;
+    }
+}
+
 double orc_loglik(int Q, const int64_t* counts, const double* p)
 {
     const int D = 1 << Q;
@@ -438,6 +462,8 @@ typedef struct {
     int32_t trace_chains;       /* first chains whose per-step values are traced */
     int32_t record_every, record_chains;
     int32_t param;              /* 0: Gaussian/gamma form (2D^2+D); 1: Algorithm 1 (4D^2) */
+    const double* povm;         /* NULL: the Pauli settings; else n_povm POVM elements (counts padded) */
+    int32_t n_povm;
 } orc_run_desc;
 
 /* Per-chain state; arrays are indexed by local chain index r in [0, n_chains). */
@@ -466,14 +492,15 @@ typedef struct {
 static int orc_K(int Q) { int K = 1; for (int q = 0; q < Q; ++q) K *= 3; return K; }
 
 /* Evaluate rho, packed rho and log L at x. */
-static double eval_state(int Q, int param, const int64_t* counts, const double* x, double* rho,
-                         double* packed, double* p)
+static double eval_state(const orc_run_desc* rd, const double* x, double* rho, double* packed, double* p)
 {
-    if (param == 1) orc_rho_bures(Q, x, rho);
+    const int Q = rd->n_qubits;
+    if (rd->param == 1) orc_rho_bures(Q, x, rho);
     else orc_rho(Q, x, rho);
     orc_pack(Q, rho, packed);
-    orc_probs(Q, rho, p);
-    return orc_loglik(Q, counts, p);
+    if (rd->povm) orc_probs_povm(Q, rho, rd->n_povm, rd->povm, p);
+    else orc_probs(Q, rho, p);
+    return orc_loglik(Q, rd->counts, p);
 }
 
 /* Initialise chains: Algorithm 2, line 1 (y^0 ~ N(0,I) from step 0's normals). */
@@ -487,7 +514,7 @@ void orc_init_chains(const orc_run_desc* rd, orc_state* st)
         double* rho = malloc(sizeof(double) * 2 * D2);
         double* p = malloc(sizeof(double) * K * D);
         orc_normals(rd->seed, chain, 0, d, x);
-        st->ll[r] = eval_state(Q, rd->param, rd->counts, x, rho, st->rho_cur + (size_t)r * D2, p);
+        st->ll[r] = eval_state(rd, x, rho, st->rho_cur + (size_t)r * D2, p);
         st->beta[r] = rd->beta0;
         st->acc_win[r] = 0;
         memset(st->s1 + (size_t)r * D2, 0, sizeof(double) * D2);
@@ -540,7 +567,7 @@ void orc_run_chains(const orc_run_desc* rd, orc_state* st)
                 const double logu1 = log(orc_da_uniform(rd->seed, chain, (uint64_t)j));
                 if (logu1 < s_prop - s_cur) {
                     ++n_s1;
-                    llp = eval_state(Q, rd->param, rd->counts, yp, rho, packed, p);
+                    llp = eval_state(rd, yp, rho, packed, p);
                     const double delta = (llp - ll) - (s_prop - s_cur);
                     accept = logu < delta;
                     if (fabs(logu - delta) < 1e-8) ++n_near;
@@ -549,7 +576,7 @@ void orc_run_chains(const orc_run_desc* rd, orc_state* st)
                 }
             } else {
                 /* line 5: rho(y') and L(y'); line 7: accept iff log alpha < dlogL */
-                llp = eval_state(Q, rd->param, rd->counts, yp, rho, packed, p);
+                llp = eval_state(rd, yp, rho, packed, p);
                 accept = logu < llp - ll;
                 if (fabs(logu - (llp - ll)) < 1e-8) ++n_near;
             }
@@ -628,6 +655,10 @@ void orc_eval_batch(int Q, const int64_t* counts, int64_t n, const double* xs,
                     double* ll_out, double* packed_out)
 {
     const int D = 1 << Q, D2 = D * D, d = 2 * D2 + D, K = orc_K(Q);
+    orc_run_desc rd;
+    memset(&rd, 0, sizeof rd);
+    rd.n_qubits = Q;
+    rd.counts = counts;
 #pragma omp parallel
     {
         double* rho = malloc(sizeof(double) * 2 * D2);
@@ -635,7 +666,7 @@ void orc_eval_batch(int Q, const int64_t* counts, int64_t n, const double* xs,
         double* p = malloc(sizeof(double) * K * D);
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
-            ll_out[i] = eval_state(Q, 0, counts, xs + (size_t)i * d, rho, packed, p);
+            ll_out[i] = eval_state(&rd, xs + (size_t)i * d, rho, packed, p);
             if (packed_out) memcpy(packed_out + (size_t)i * D2, packed, sizeof(double) * D2);
         }
         free(rho);

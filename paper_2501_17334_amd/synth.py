@@ -120,6 +120,56 @@ def sample_counts(dist, shots, rng):
 
 
 @dataclass
+class PovmProblem:
+    """A measurement other than the Pauli settings: POVM elements [n, D, D]
+    with one count each."""
+    name: str
+    n_qubits: int
+    povm: np.ndarray
+    counts: np.ndarray
+    truth: TruthState
+    seed: int
+
+
+def random_bases_problem(Q, shots=1024, n_bases=None, white=0.1, index=0) -> PovmProblem:
+    """n_bases (default 3^Q) Haar-random orthonormal bases U_k (scipy's
+    unitary_group); the POVM elements are the projectors onto the columns
+    u_kl of each U_k, and the counts of basis k are a multinomial sample of
+    the diagonal of U_k^dag rho U_k (the state rotated into the basis and read
+    out).  Truth: a Haar pure state with white noise."""
+    from scipy.stats import unitary_group
+    rng = np.random.default_rng([DATA_SEED, 91, Q, index])
+    D = 2 ** Q
+    K = n_bases or 3 ** Q
+    bases = [unitary_group.rvs(D, random_state=rng) for _ in range(K)]
+    st = _noisy_pure(Q, haar_vector(D, rng), white)
+    rho = st.density_matrix()
+    povm = np.stack([np.outer(U[:, l], U[:, l].conj()) for U in bases for l in range(D)])
+    dist = np.stack([np.real(np.diag(U.conj().T @ rho @ U)) for U in bases])
+    counts = sample_counts(dist, shots, rng).reshape(-1)
+    return PovmProblem(f"bases_{Q}", Q, povm, counts, st, CHAIN_SEED + 200 + Q)
+
+
+def sic_qubit_problem(shots=4000, white=0.1) -> PovmProblem:
+    """The qubit SIC-POVM: Pi_m = (I + n_m . sigma) / 4 with n_m the vertices
+    of a regular tetrahedron; the outcome probabilities of a state with Bloch
+    vector r are (1 + n_m . r) / 4.  Truth: a Haar pure state with white noise."""
+    rng = np.random.default_rng([DATA_SEED, 92])
+    n = np.array([[0.0, 0.0, 1.0], [2 * np.sqrt(2) / 3, 0.0, -1 / 3],
+                  [-np.sqrt(2) / 3, np.sqrt(2 / 3), -1 / 3], [-np.sqrt(2) / 3, -np.sqrt(2 / 3), -1 / 3]])
+    sx = np.array([[0, 1], [1, 0]], dtype=complex)
+    sy = np.array([[0, -1j], [1j, 0]])
+    sz = np.array([[1, 0], [0, -1]], dtype=complex)
+    povm = np.stack([(np.eye(2) + v[0] * sx + v[1] * sy + v[2] * sz) / 4 for v in n])
+    st = _noisy_pure(1, haar_vector(2, rng), white)
+    rho = st.density_matrix()
+    r = np.array([2 * rho[0, 1].real, -2 * rho[0, 1].imag, (rho[0, 0] - rho[1, 1]).real])
+    p = np.clip((1 + n @ r) / 4, 0.0, None)
+    counts = rng.multinomial(shots, p / p.sum()).astype(np.int64)
+    return PovmProblem("sic_1", 1, povm, counts, st, CHAIN_SEED + 300)
+
+
+@dataclass
 class Problem:
     name: str
     n_qubits: int
