@@ -109,6 +109,18 @@ typedef struct {
     qst_path path;
     int32_t device;          /* HIP device ordinal the handle lives on */
     qst_param param;         /* parameterisation; QST_PARAM_GAMMA when zero-initialised */
+    /* Optional measurement other than the Pauli settings (NULL: all 3^Q
+     * Pauli settings).  povm: host, n_povm complex D x D Hermitian matrices
+     * Pi_m (row-major, interleaved), copied; p_m = Tr(Pi_m rho); counts then
+     * holds n_povm entries, the likelihood is sum_m c_m log p_m (Eq.
+     * (likelihood) with the Pi_m in place of the Lambda_kl).  1 <= n_povm <=
+     * 3^Q 2^Q, 1..4 qubits, the dense path (QST_PATH_AUTO picks it) in FP64
+     * or FP32; QST_ERR_UNSUPPORTED for the Kronecker path or BF16x3,
+     * QST_ERR_INVALID for a non-Hermitian or non-finite element.  Elements
+     * need not sum to the identity; one with p_m <= 0 and c_m > 0 gives
+     * log L = -inf. */
+    const double* povm;
+    int32_t n_povm;
 } qst_problem_desc;
 
 /* Frozen MLP surrogate s(x) of log L for delayed acceptance (Christen & Fox

@@ -144,11 +144,40 @@ std::vector<double> pauli_matrix_packed(int Q)
 
 // M in MFMA A-operand fragment order (see the dense contraction in
 // chain_kernel.hpp), as raw bytes of the requested precision.
-std::vector<uint8_t> pauli_fragments(int Q, int prec)
+// The packed-real measurement matrix of user POVM elements (n complex D x D
+// matrices, row-major, interleaved), padded with zero rows to 3^Q 2^Q:
+// p_m = Tr(Pi_m rho) = sum_a Re Pi_aa rho_aa + sum_{a<b} 2 (Re Pi_ab Re rho_ab +
+// Im Pi_ab Im rho_ab), so row m holds Re Pi_aa at (a, a), 2 Re Pi_ab at (a, b)
+// and 2 Im Pi_ab at (b, a) for a < b, against the packed form of rho.
+std::vector<double> povm_matrix_packed(int Q, const double* povm, int n)
+{
+    const int D = 1 << Q, D2 = D * D, KD = ipow3(Q) * D;
+    std::vector<double> M(static_cast<size_t>(KD) * D2, 0.0);
+    for (int m = 0; m < n; ++m) {
+        const double* P = povm + static_cast<size_t>(m) * 2 * D2;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) {
+                const double re = P[2 * (a * D + b)], im = P[2 * (a * D + b) + 1];
+                const double re_t = P[2 * (b * D + a)], im_t = P[2 * (b * D + a) + 1];
+                if (!std::isfinite(re) || !std::isfinite(im)) fail(QST_ERR_INVALID, "POVM element not finite");
+                if (std::fabs(re - re_t) > 1e-12 || std::fabs(im + im_t) > 1e-12)
+                    fail(QST_ERR_INVALID, "POVM element not Hermitian");
+                double* row = M.data() + static_cast<size_t>(m) * D2;
+                if (a == b) row[a * D + a] = re;
+                else if (a < b) {
+                    row[a * D + b] = 2.0 * re;
+                    row[b * D + a] = 2.0 * im;
+                }
+            }
+    }
+    return M;
+}
+
+// The measurement matrix in the dense kernels' MFMA operand order.
+std::vector<uint8_t> matrix_fragments(int Q, const std::vector<double>& M, int prec)
 {
     const int D = 1 << Q, D2 = D * D, KD = ipow3(Q) * D;
     const int NT = (KD + 15) / 16;
-    const std::vector<double> M = pauli_matrix_packed(Q);
     auto m_at = [&](int row, int col) { return (row < KD && col < D2) ? M[static_cast<size_t>(row) * D2 + col] : 0.0; };
     std::vector<uint8_t> out;
     if (prec == qst::kPrecF64 || prec == qst::kPrecF32) {
@@ -175,7 +204,7 @@ std::vector<uint8_t> pauli_fragments(int Q, int prec)
                         const float f = static_cast<float>(m_at(16 * nt + l % 16, 32 * ks + 8 * (l / 16) + v));
                         uint32_t bits;
                         std::memcpy(&bits, &f, 4);
-                        if ((bits & 0xFFFFu) != 0) fail(QST_ERR_DEVICE, "Pauli matrix entry not exact in BF16");
+                        if ((bits & 0xFFFFu) != 0) fail(QST_ERR_DEVICE, "measurement matrix entry not exact in BF16");
                         h[((static_cast<size_t>(nt) * KS + ks) * 64 + l) * 8 + v] = static_cast<uint16_t>(bits >> 16);
                     }
     }
@@ -351,6 +380,7 @@ struct qst_problem {
     qst_path path = QST_PATH_KRON;
     qst_param param = QST_PARAM_GAMMA;
     std::vector<int64_t> counts;
+    std::vector<double> povm_M;   // user POVM: packed measurement matrix (empty: the Pauli settings)
     double* nd = nullptr;  // counts as doubles
     uint16_t* mu = nullptr;  // Pauli index of every (setting, transform position), [KD]
     double* ndv = nullptr;   // counts in the task-major order of the likelihood transforms, [KD]
@@ -361,7 +391,8 @@ struct qst_problem {
     {
         if (!mfrag[prec]) {
             if (Q > 4) fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
-            const std::vector<uint8_t> f = pauli_fragments(Q, prec);
+            const std::vector<uint8_t> f =
+                matrix_fragments(Q, povm_M.empty() ? pauli_matrix_packed(Q) : povm_M, prec);
             void* d = dev_alloc<uint8_t>(f.size());
             hipError_t e = hipMemcpy(d, f.data(), f.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) {
@@ -523,9 +554,26 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
             fail(QST_ERR_UNSUPPORTED, "the Kronecker path runs in FP64 or FP32; BF16x3 needs QST_PATH_DENSE");
         if (p->path == QST_PATH_DENSE && Q > 4)
             fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
+        if (desc->povm) {
+            // user POVM elements: the dense contraction against their matrix
+            if (desc->n_povm < 1 || desc->n_povm > p->KD)
+                fail(QST_ERR_INVALID, "n_povm must be in 1..3^Q 2^Q");
+            if (desc->path == QST_PATH_KRON)
+                fail(QST_ERR_UNSUPPORTED, "user POVMs need the dense path (the Kronecker route is for Pauli settings)");
+            if (desc->precision == QST_BF16X3)
+                fail(QST_ERR_UNSUPPORTED, "user POVMs run in FP64 or FP32 (BF16x3 needs a matrix exact in BF16)");
+            if (Q > 4) fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
+            p->path = QST_PATH_DENSE;
+        }
         if (p->param == QST_PARAM_BURES && (p->path != QST_PATH_KRON || Q > 4))
             fail(QST_ERR_UNSUPPORTED, "Algorithm 1 (QST_PARAM_BURES) runs on the Kronecker path, 1..4 qubits");
-        p->counts.assign(desc->counts, desc->counts + p->KD);
+        if (desc->povm) {
+            p->povm_M = povm_matrix_packed(Q, desc->povm, desc->n_povm);
+            p->counts.assign(p->KD, 0);
+            std::copy(desc->counts, desc->counts + desc->n_povm, p->counts.begin());
+        } else {
+            p->counts.assign(desc->counts, desc->counts + p->KD);
+        }
         std::vector<double> nd(p->KD);
         for (int i = 0; i < p->KD; ++i) {
             if (p->counts[i] < 0) fail(QST_ERR_INVALID, "negative count");
@@ -955,6 +1003,10 @@ qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double
         if (n == 0) return;
         if (!rho || !ll_out) fail(QST_ERR_INVALID, "NULL buffer");
         const qst_path pth = path == QST_PATH_AUTO ? p->path : path;
+        if (pth == QST_PATH_KRON && !p->povm_M.empty())
+            fail(QST_ERR_UNSUPPORTED, "user POVMs need the dense path");
+        if (precision == QST_BF16X3 && !p->povm_M.empty())
+            fail(QST_ERR_UNSUPPORTED, "user POVMs run in FP64 or FP32");
         if (precision != QST_FP64 && precision != QST_FP32 && precision != QST_BF16X3)
             fail(QST_ERR_INVALID, "unknown precision");
         if (pth == QST_PATH_KRON && precision == QST_BF16X3)

@@ -32,7 +32,8 @@ class QstError(RuntimeError):
 
 class _ProblemDesc(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("counts", C.POINTER(C.c_int64)),
-                ("precision", C.c_int), ("path", C.c_int), ("device", C.c_int32), ("param", C.c_int)]
+                ("precision", C.c_int), ("path", C.c_int), ("device", C.c_int32), ("param", C.c_int),
+                ("povm", C.POINTER(C.c_double)), ("n_povm", C.c_int32)]
 
 
 # parameterisation of rho(x): the Gaussian/gamma form (2D^2+D parameters) or
@@ -170,17 +171,28 @@ class RunConfig:
 class Problem:
     """A tomography problem on one GPU (qst_init_problem / qst_free_problem)."""
 
-    def __init__(self, n_qubits, counts, precision="fp64", path="auto", device=0, param="gamma"):
+    def __init__(self, n_qubits, counts, precision="fp64", path="auto", device=0, param="gamma", povm=None):
+        """povm: optional [n, D, D] complex POVM elements in place of the Pauli
+        settings (counts then has n entries; dense path, FP64 or FP32)."""
         self.Q = int(n_qubits)
         self.D = 2 ** self.Q
         self.K = 3 ** self.Q
         self.param = param
         self.d = 4 * self.D * self.D if param == "bures" else 2 * self.D * self.D + self.D
         self.counts = np.ascontiguousarray(counts, dtype=np.int64).reshape(-1)
-        if self.counts.size != self.K * self.D:
+        self._povm = None
+        n_povm = 0
+        if povm is not None:
+            povm = np.asarray(povm, dtype=complex)
+            n_povm = povm.shape[0]
+            if povm.shape != (n_povm, self.D, self.D) or self.counts.size != n_povm:
+                raise ValueError("povm must be [n, D, D] with one count per element")
+            self._povm = np.ascontiguousarray(np.stack([povm.real, povm.imag], axis=-1))
+        elif self.counts.size != self.K * self.D:
             raise ValueError("counts must have 3^Q * 2^Q entries")
         desc = _ProblemDesc(self.Q, self.counts.ctypes.data_as(C.POINTER(C.c_int64)),
-                            _PREC[precision], _PATH[path], device, _PARAM[param])
+                            _PREC[precision], _PATH[path], device, _PARAM[param],
+                            _f64(self._povm) if self._povm is not None else None, n_povm)
         h = C.c_void_p()
         _check(lib().qst_init_problem(C.byref(desc), C.byref(h)))
         self._h = h
