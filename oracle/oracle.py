@@ -40,7 +40,7 @@ class _RunDesc(C.Structure):
                 ("adapt_factor", C.c_double), ("adapt_until", C.c_int64), ("seed", C.c_uint64),
                 ("surrogate", C.POINTER(_Mlp)), ("trace_chains", C.c_int32),
                 ("record_every", C.c_int32), ("record_chains", C.c_int32), ("param", C.c_int32),
-                ("povm", c_double_p), ("n_povm", C.c_int32)]
+                ("povm", c_double_p), ("n_povm", C.c_int32), ("alpha", C.c_double)]
 
 
 class _State(C.Structure):
@@ -69,6 +69,10 @@ def lib():
         L.orc_da_uniform.restype = C.c_double
         L.orc_rho.argtypes = [C.c_int, c_double_p, c_double_p]
         L.orc_rho_bures.argtypes = [C.c_int, c_double_p, c_double_p]
+        L.orc_rho_dirichlet.argtypes = [C.c_int, c_double_p, C.c_double, c_double_p]
+        L.orc_gamma_quantile.argtypes = [C.c_double, C.c_double]
+        L.orc_gamma_quantile.restype = C.c_double
+        L.orc_gamma_pq.argtypes = [C.c_double, C.c_double, c_double_p, c_double_p]
         L.orc_bures_unitary.argtypes = [C.c_int, c_double_p, c_double_p]
         L.orc_param_dim.argtypes = [C.c_int, C.c_int]
         L.orc_param_dim.restype = C.c_int
@@ -102,7 +106,7 @@ def num_threads():
 
 # parameterisations: the Gaussian/gamma form (2D^2+D parameters) and the
 # paper's Algorithm 1, the Bures draw (4D^2 parameters)
-PARAMS = {"gamma": 0, "bures": 1}
+PARAMS = {"gamma": 0, "bures": 1, "dirichlet": 2}
 
 
 def dims(Q, param="gamma"):
@@ -140,14 +144,29 @@ def da_uniform(seed, chain, step):
     return lib().orc_da_uniform(seed, chain, step)
 
 
-def rho_of_x(Q, x, param="gamma"):
-    """rho(x) as a D x D complex matrix (param "bures": Algorithm 1)."""
+def rho_of_x(Q, x, param="gamma", alpha=0.5):
+    """rho(x) as a D x D complex matrix (param "bures": Algorithm 1;
+    "dirichlet": Gamma(alpha)-quantile weights)."""
     D, _, d = dims(Q, param)
     x = np.ascontiguousarray(x, dtype=np.float64)
     assert x.shape == (d,)
     out = np.zeros(2 * D * D)
-    (lib().orc_rho_bures if param == "bures" else lib().orc_rho)(Q, _p(x), _p(out))
+    if param == "dirichlet":
+        lib().orc_rho_dirichlet(Q, _p(x), alpha, _p(out))
+    else:
+        (lib().orc_rho_bures if param == "bures" else lib().orc_rho)(Q, _p(x), _p(out))
     return out.reshape(D, D, 2) @ np.array([1.0, 1j])
+
+
+def gamma_quantile(a, v):
+    """P^{-1}(a, Phi(v)): the Gamma(a) quantile of the normal probability of v."""
+    return lib().orc_gamma_quantile(a, v)
+
+
+def gamma_pq(a, x):
+    P, Qc = np.zeros(1), np.zeros(1)
+    lib().orc_gamma_pq(a, x, _p(P), _p(Qc))
+    return P[0], Qc[0]
 
 
 def bures_unitary(Q, x):
@@ -275,6 +294,7 @@ class RunParams:
     surrogate: MlpWeights | None = None
     param: str = "gamma"            # "bures": Algorithm 1 (4D^2 parameters)
     povm: np.ndarray | None = None  # [n, D, D] POVM elements (counts then has n entries)
+    alpha: float = 0.5              # param "dirichlet": concentration of the weights
 
 
 class Chains:
@@ -316,7 +336,7 @@ class Chains:
                         p.adapt_lo, p.adapt_hi, p.adapt_factor, p.adapt_until, p.seed,
                         self._mlp, p.trace_chains, p.record_every, p.record_chains,
                         PARAMS[p.param], _p(self._povm),
-                        0 if p.povm is None else int(p.povm.shape[0]))
+                        0 if p.povm is None else int(p.povm.shape[0]), float(p.alpha))
 
     def _state(self, n_steps, bufs):
         R = self.p.n_chains

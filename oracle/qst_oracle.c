@@ -187,7 +187,7 @@ void orc_rho(int Q, const double* x, double* rho_out)
 int orc_param_dim(int Q, int param)
 {
     const int D = 1 << Q, D2 = D * D;
-    return param == 1 ? 4 * D2 : 2 * D2 + D;
+    return param == 1 ? 4 * D2 : 2 * D2 + D;   /* param 2 (Dirichlet alpha) as 0 */
 }
 
 /* Householder QR of the D x D complex matrix A (row-major, overwritten by R
@@ -290,6 +290,78 @@ void orc_rho_bures(int Q, const double* x, double* rho_out)
     free(u);
     free(Gm);
     free(W);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Dirichlet weights of general concentration alpha (the paper's "other      */
+/* priors"): gamma_j = P^{-1}(alpha, Phi(v_j)), the Gamma(alpha) quantile of   */
+/* the normal probability of v_j, so that x ~ N(0, I) still maps to the      */
+/* prior; w_j = gamma_j / sum_k gamma_k.                                      */
+/* ----------------------------------------------------------------------- */
+/* Regularised incomplete gamma functions for a > 0, x > 0: the power series
+ * P = x^a e^-x / Gamma(a+1) sum_n x^n / ((a+1)...(a+n)) below x = a + 1, the
+ * Legendre continued fraction of Q = 1 - P above it (evaluated from the
+ * bottom up with a fixed depth). */
+static double gamma_prefactor(double a, double x) { return exp(a * log(x) - x - lgamma(a)); }
+
+void orc_gamma_pq(double a, double x, double* P, double* Qc)
+{
+    if (x <= 0.0) { *P = 0.0; *Qc = 1.0; return; }
+    if (x < a + 1.0) {
+        double term = 1.0 / a, sum = term;
+        for (int n = 1; n < 10000; ++n) {
+            term *= x / (a + n);
+            sum += term;
+            if (term < sum * 1e-17) break;
+        }
+        *P = sum * gamma_prefactor(a, x);
+        *Qc = 1.0 - *P;
+    } else {
+        /* Q = prefactor / (x + 1 - a - 1(1-a)/(x + 3 - a - 2(2-a)/(x + 5 - a - ...))) */
+        double f = x + 2.0 * 400 + 1.0 - a;
+        for (int n = 400; n >= 1; --n) f = x + 2.0 * n - 1.0 - a - (double)n * (n - a) / f;
+        *Qc = gamma_prefactor(a, x) / f;
+        *P = 1.0 - *Qc;
+    }
+}
+
+/* x with P(a, x) = u (v <= 0, u = Phi(v)) or Q(a, x) = q (v > 0, q = Phi(-v)):
+ * bisection on log x until the bracket stops shrinking. */
+double orc_gamma_quantile(double a, double v)
+{
+    const double u = 0.5 * erfc(-v / sqrt(2.0));
+    const double q = 0.5 * erfc(v / sqrt(2.0));
+    double lo = -800.0, hi = 10.0;             /* log x */
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        double P, Qc;
+        orc_gamma_pq(a, exp(mid), &P, &Qc);
+        const int below = v <= 0.0 ? (P < u) : (Qc > q);
+        if (below) lo = mid;
+        else hi = mid;
+    }
+    return exp(0.5 * (lo + hi));
+}
+
+/* rho(x) = sum_j w_j z_j z_j^dag / |z_j|^2 with w_j from the Gamma(alpha)
+ * quantiles of the v_j (same x layout as orc_rho). */
+void orc_rho_dirichlet(int Q, const double* x, double alpha, double* rho_out)
+{
+    const int D = 1 << Q, D2 = D * D;
+    double* y = malloc(sizeof(double) * (2 * D2 + D));
+    double* g = malloc(sizeof(double) * D);
+    double gs = 0.0;
+    for (int j = 0; j < D; ++j) {
+        g[j] = orc_gamma_quantile(alpha, x[2 * D2 + j]);
+        gs += g[j];
+    }
+    /* orc_rho takes weights v_j^2 / sum v^2: hand it v_j = sqrt(gamma_j) */
+    memcpy(y, x, sizeof(double) * 2 * D2);
+    for (int j = 0; j < D; ++j) y[2 * D2 + j] = sqrt(g[j] / gs);
+    orc_rho(Q, y, rho_out);
+    free(y);
+    free(g);
 }
 
 /* Packed real form of a Hermitian matrix given as interleaved complex. */
@@ -464,6 +536,7 @@ typedef struct {
     int32_t param;              /* 0: Gaussian/gamma form (2D^2+D); 1: Algorithm 1 (4D^2) */
     const double* povm;         /* NULL: the Pauli settings; else n_povm POVM elements (counts padded) */
     int32_t n_povm;
+    double alpha;               /* param 2: Dirichlet concentration of the weights */
 } orc_run_desc;
 
 /* Per-chain state; arrays are indexed by local chain index r in [0, n_chains). */
@@ -496,6 +569,7 @@ static double eval_state(const orc_run_desc* rd, const double* x, double* rho, d
 {
     const int Q = rd->n_qubits;
     if (rd->param == 1) orc_rho_bures(Q, x, rho);
+    else if (rd->param == 2) orc_rho_dirichlet(Q, x, rd->alpha, rho);
     else orc_rho(Q, x, rho);
     orc_pack(Q, rho, packed);
     if (rd->povm) orc_probs_povm(Q, rho, rd->n_povm, rd->povm, p);
