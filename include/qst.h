@@ -89,7 +89,7 @@ typedef enum {
  * in both; the state x of qst_chain_state has d entries. */
 typedef enum {
     QST_PARAM_GAMMA = 0,  /* the Gaussian/gamma-derived form above, d = 2 D^2 + D */
-    QST_PARAM_BURES = 1   /* Algorithm 1, the Bures draw, d = 4 D^2: G = x[0:D^2] +
+    QST_PARAM_BURES = 1,  /* Algorithm 1, the Bures draw, d = 4 D^2: G = x[0:D^2] +
                              i x[D^2:2D^2], H = x[2D^2:3D^2] + i x[3D^2:4D^2], both
                              filled column by column (entry (i,j) at offset jD+i);
                              U = Q Lambda for H = QR with Lambda = diag(r_kk/|r_kk|)
@@ -98,6 +98,12 @@ typedef enum {
                              rho = W W^dag / Tr(W W^dag).  Kronecker path only
                              (FP64 or FP32), 1..4 qubits, single-problem runs
                              without a surrogate (QST_ERR_UNSUPPORTED otherwise) */
+    QST_PARAM_DIRICHLET = 2 /* the default form with Dirichlet(alpha) weights, d = 2 D^2 + D:
+                             gamma_j = P^{-1}(alpha, Phi(v_j)), the Gamma(alpha) quantile
+                             of the normal probability of v_j (so x ~ N(0, I) maps to the
+                             prior), w_j = gamma_j / sum_k gamma_k; alpha from
+                             qst_problem_desc.alpha > 0.  Kronecker path (FP64 or FP32),
+                             1..6 qubits, single-problem runs without a surrogate */
 } qst_param;
 
 typedef struct qst_problem qst_problem;   /* opaque; owns every device buffer behind it */
@@ -121,6 +127,7 @@ typedef struct {
      * log L = -inf. */
     const double* povm;
     int32_t n_povm;
+    double alpha;            /* QST_PARAM_DIRICHLET: concentration alpha > 0 (ignored otherwise) */
 } qst_problem_desc;
 
 /* Frozen MLP surrogate s(x) of log L for delayed acceptance (Christen & Fox

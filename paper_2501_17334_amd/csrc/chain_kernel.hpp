@@ -79,6 +79,7 @@ struct ChainArgs {
     double beta0;
     double adapt_lo, adapt_hi, adapt_factor;
     uint64_t seed;
+    double alpha, lg_alpha;  // Dirichlet weights: concentration and lgamma(alpha)
     int32_t trace_chains;
     double* tr_ll;
     double* tr_lu;
@@ -98,9 +99,10 @@ struct ChainArgs {
 
 // How p = Tr(Lambda rho) is formed inside the chain step.
 enum : int { kPathKron = 0, kPathDense = 1 };
-// Parameterisation rho(x): the Gaussian/gamma form (d = 2D^2 + D) or the
-// paper's Algorithm 1, the Bures draw (d = 4D^2).
-enum : int { kParamGamma = 0, kParamBures = 1 };
+// Parameterisation rho(x): the Gaussian/gamma form (d = 2D^2 + D), the
+// paper's Algorithm 1, the Bures draw (d = 4D^2), or the Gaussian/gamma form
+// with Dirichlet(alpha) weights (d = 2D^2 + D).
+enum : int { kParamGamma = 0, kParamBures = 1, kParamDirichlet = 2 };
 
 template <int Q, int PARAM>
 struct ParamDims {
@@ -300,17 +302,105 @@ __device__ __forceinline__ int packed_slot(int lane, int e)
     }
 }
 
-// Column weights w_j = (v_j^2 / sum_k v_k^2) / |z_j|^2 from the parameters in
-// ybuf (x layout).
+// ---------------------------------------------------------------------------
+// Dirichlet(alpha) weights: gamma_j = P^{-1}(alpha, Phi(v_j)), the Gamma(alpha)
+// quantile of the normal probability of v_j, so that x ~ N(0, I) maps to
+// Dirichlet(alpha) weights w_j = gamma_j / sum_k gamma_k and the pCN ratio of
+// Algorithm 2 stays exact.
+// ---------------------------------------------------------------------------
+// Regularised incomplete gamma at x = e^t (a > 0): P by its power series
+// below x = a + 1, Q = 1 - P by the Legendre continued fraction (modified
+// Lentz) above it; returns the one that is accurate (P below, Q above) with
+// `upper` telling which.
+__device__ __forceinline__ double gamma_pq_dev(double a, double t, double lg_a, bool& upper)
+{
+    const double x = exp(t);
+    const double pre = exp(a * t - x - lg_a);   // x^a e^-x / Gamma(a)
+    if (x < a + 1.0) {
+        upper = false;
+        double term = 1.0 / a, sum = term;
+        for (int n = 1; n < 500; ++n) {
+            term *= x / (a + n);
+            sum += term;
+            if (term < sum * 1e-17) break;
+        }
+        return sum * pre;
+    }
+    upper = true;
+    // Q = pre / (b1 - 1(1-a) / (b2 - 2(2-a) / (b3 - ...))), b_n = x + 2n - 1 - a
+    const double tiny = 1e-300;
+    double b = x + 1.0 - a, c = 1.0 / tiny, dd = 1.0 / b, h = dd;
+    for (int n = 1; n < 500; ++n) {
+        const double an = -n * (n - a);
+        b += 2.0;
+        dd = an * dd + b;
+        if (fabs(dd) < tiny) dd = tiny;
+        c = b + an / c;
+        if (fabs(c) < tiny) c = tiny;
+        dd = 1.0 / dd;
+        const double del = dd * c;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return pre * h;
+}
+
+// log x of the Gamma(a) quantile at probability Phi(v): Newton steps on
+// t = log x for P(a, e^t) = Phi(v) (v <= 0) or Q(a, e^t) = Phi(-v) (v > 0),
+// both increasing in t with derivative x^a e^-x / Gamma(a); started from the
+// Wilson-Hilferty cube (whose normal quantile is v itself) or, where that is
+// not positive, from the leading term of the series.
+__device__ __forceinline__ double gamma_quantile_log(double a, double v, double lg_a)
+{
+    const double target = 0.5 * erfc((v <= 0.0 ? -v : v) * 0.70710678118654752440);   // Phi(-|v|)
+    const double c = 1.0 / (9.0 * a);
+    const double wh = 1.0 - c + v * sqrt(c);
+    double t = wh > 0.1 ? log(a) + 3.0 * log(wh)
+                        : (v <= 0.0 ? (log(target) + lg_a + log(a)) / a : log(a + 1.0) - log(target));
+    for (int it = 0; it < 60; ++it) {
+        bool upper;
+        const double f = gamma_pq_dev(a, t, lg_a, upper);
+        // residual of the increasing function of t: P - u, or (1 - Q) - (1 - q) = q - Q
+        double r;
+        if (v <= 0.0) r = upper ? (1.0 - f) - target : f - target;
+        else r = upper ? target - f : (f - (1.0 - target));
+        const double dens = exp(a * t - exp(t) - lg_a);
+        double step = r / dens;
+        step = fmax(fmin(step, 2.0), -2.0);
+        t -= step;
+        if (fabs(step) < 1e-15 * fmax(1.0, fabs(t))) break;
+    }
+    return t;
+}
+
+// v_j = sqrt(gamma_j / sum_k gamma_k) into vbuf (the team's LDS), so that the
+// weights of stage_rho, v_j^2 / sum_k v_k^2, are the Dirichlet weights.
 template <int Q, int G>
-__device__ __forceinline__ void stage_weights(const double* ybuf, double* wt, int lane)
+__device__ __forceinline__ void stage_dirichlet_v(const double* ybuf, double* vbuf, double alpha, double lg_alpha,
+                                                  double* scratch, int lane)
+{
+    constexpr int D = 1 << Q, D2 = D * D;
+    for (int j = lane; j < D; j += G) vbuf[j] = exp(gamma_quantile_log(alpha, ybuf[2 * D2 + j], lg_alpha));
+    team_sync<G>();
+    double part = 0.0;
+    for (int j = lane; j < D; j += G) part += vbuf[j];
+    const double gs = team_sum<G>(part, scratch, lane);
+    team_sync<G>();
+    for (int j = lane; j < D; j += G) vbuf[j] = sqrt(vbuf[j] / gs);
+    team_sync<G>();
+}
+
+// Column weights w_j = (v_j^2 / sum_k v_k^2) / |z_j|^2 from Z in ybuf (x
+// layout) and v in vbuf.
+template <int Q, int G>
+__device__ __forceinline__ void stage_weights(const double* ybuf, const double* vbuf, double* wt, int lane)
 {
     using Dm = Dims<Q>;
     constexpr int D = Dm::D, D2 = Dm::D2;
     double V = 0.0;
 #pragma unroll 4
     for (int j = 0; j < D; ++j) {
-        const double v = ybuf[2 * D2 + j];
+        const double v = vbuf[j];
         V += v * v;
     }
     for (int j = lane; j < D; j += G) {
@@ -320,7 +410,7 @@ __device__ __forceinline__ void stage_weights(const double* ybuf, double* wt, in
             const double im = ybuf[D2 + j * D + i];
             nz += re * re + im * im;
         }
-        const double v = ybuf[2 * D2 + j];
+        const double v = vbuf[j];
         const double w = (v * v / V) / nz;
         wt[j] = w;
     }
@@ -328,9 +418,10 @@ __device__ __forceinline__ void stage_weights(const double* ybuf, double* wt, in
 
 // Packed rho = sum_j w_j z_j z_j^dag into rhoP (LDS) and rp (this lane's
 // slots): entry (a, b) is sum_j w_j Re(z_aj conj z_bj) for a <= b and
-// sum_j w_j Im(z_bj conj z_aj) for a > b.
+// sum_j w_j Im(z_bj conj z_aj) for a > b.  Z from ybuf (x layout), the
+// weight parameters v_j from vbuf (x[2D^2 + j], or their Dirichlet form).
 template <int Q, int G>
-__device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double* rhoP,
+__device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf, double* wt, double* rhoP,
                                           double (&rp)[TeamShape<Q, G>::NPL], int lane)
 {
     using Dm = Dims<Q>;
@@ -347,7 +438,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
         double V = 0.0;
 #pragma unroll 4
         for (int j = 0; j < D; ++j) {
-            const double v = ybuf[2 * D2 + j];
+            const double v = vbuf[j];
             V += v * v;
         }
         {
@@ -364,7 +455,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
             if constexpr (LPC >= 4) nz += xor_lane<2>(nz);
             if constexpr (LPC >= 8) nz += xor_lane<4>(nz);
             if (q == 0) {
-                const double v = ybuf[2 * D2 + j];
+                const double v = vbuf[j];
                 wt[j] = sqrt((v * v / V) / nz);
             }
         }
@@ -409,7 +500,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
         double V = 0.0;
 #pragma unroll 4
         for (int j = 0; j < D; ++j) {
-            const double v = ybuf[2 * D2 + j];
+            const double v = vbuf[j];
             V += v * v;
         }
         double zr[4], zi[4];
@@ -423,7 +514,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
             nz += xor_lane<2>(nz);
             nz += xor_lane<4>(nz);
             nz += xor_lane<8>(nz);
-            const double v = ybuf[2 * D2 + j];
+            const double v = vbuf[j];
             const double sj = fabs(v) * rsqrt_f64(V * nz);   // sqrt(w_j)
             zr[t] *= sj;
             zi[t] *= sj;
@@ -445,7 +536,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
             rhoP[row * 16 + col] = v;
         }
     } else {
-        stage_weights<Q, G>(ybuf, wt, lane);
+        stage_weights<Q, G>(ybuf, vbuf, wt, lane);
         team_sync<G>();
 #pragma unroll 1
         for (int e = 0; e < S::NPL; ++e) {
@@ -475,10 +566,10 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double
 // The same without the register copy: packed rho' stays in rhoP only, where
 // each lane finds its own slots p = packed_slot(lane, e) again.
 template <int Q, int G>
-__device__ __forceinline__ void stage_rho(const double* ybuf, double* wt, double* rhoP, int lane)
+__device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf, double* wt, double* rhoP, int lane)
 {
     double unused[TeamShape<Q, G>::NPL];
-    stage_rho<Q, G>(ybuf, wt, rhoP, unused, lane);
+    stage_rho<Q, G>(ybuf, vbuf, wt, rhoP, unused, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1186,7 +1277,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G, PATH, PARAM>;
-    static_assert(PARAM == kParamGamma || (PATH == kPathKron && Q <= 4 && G <= 64),
+    static_assert(PARAM != kParamBures || (PATH == kPathKron && Q <= 4 && G <= 64),
                   "Algorithm 1 runs on the Kronecker path with one-wavefront teams");
     static_assert(PATH == kPathKron ? (PREC == kPrecF64 || PREC == kPrecF32) : (G == 64 && WG == 1024),
                   "unsupported path");
@@ -1308,8 +1399,15 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     };
 
     auto evaluate = [&]() -> double {
-        if constexpr (PARAM == kParamBures) stage_rho_bures<Q, G>(ybuf, pauli, rhoP, misc, lane);
-        else stage_rho<Q, G>(ybuf, wt, rhoP, lane);
+        if constexpr (PARAM == kParamBures) {
+            stage_rho_bures<Q, G>(ybuf, pauli, rhoP, misc, lane);
+        } else if constexpr (PARAM == kParamDirichlet) {
+            // v in the Pauli region; misc[0] holds the uniform, the sum uses misc[4..]
+            stage_dirichlet_v<Q, G>(ybuf, pauli, A.alpha, A.lg_alpha, misc + 4, lane);
+            stage_rho<Q, G>(ybuf, pauli, wt, rhoP, lane);
+        } else {
+            stage_rho<Q, G>(ybuf, ybuf + 2 * D2, wt, rhoP, lane);
+        }
         sync();
         if constexpr (PATH == kPathDense) {
             return dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, PATH>::kOffRed, A.mfrag, A.nd, logtab, tid);

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_da_exact(DaAr
     for (int i = lane; i < d; i += G) ybuf[i] = P.yprop[c * d + i];
     __syncthreads();
     double rp[S::NPL];
-    stage_rho<Q, G>(ybuf, wt, rhoP, rp, lane);
+    stage_rho<Q, G>(ybuf, ybuf + 2 * D2, wt, rhoP, rp, lane);
     __syncthreads();
     stage_pauli<Q, G>(rhoP, pauli, lane);
     __syncthreads();

@@ -283,6 +283,21 @@ void launch_loglik_t(const double* nd, const uint16_t* mu, const double* ndv, co
     hip_check(hipGetLastError(), "loglik kernel launch");
 }
 
+// Dirichlet(alpha) weights: the Kronecker route with the default team shape
+// of each qubit count.
+void launch_chains_dirichlet(int Q, int prec, const qst::ChainArgs& a, hipStream_t s)
+{
+    using namespace qst;
+#define QST_DIR(q, g, wg)                                                                               \
+    if (Q == q)                                                                                         \
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamDirichlet>(a, s) \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamDirichlet>(a, s);
+    QST_DIR(1, 8, 64) QST_DIR(2, 16, 64) QST_DIR(3, 32, 64) QST_DIR(4, 64, 256) QST_DIR(5, 256, 256)
+    QST_DIR(6, 512, 512)
+#undef QST_DIR
+    fail(QST_ERR_INVALID, "n_qubits must be in 1..6");
+}
+
 // Algorithm 1 (the Bures draw): the Kronecker route with one fixed team
 // shape per qubit count (one wavefront per chain at 4 qubits).
 void launch_chains_bures(int Q, int prec, const qst::ChainArgs& a, hipStream_t s)
@@ -379,6 +394,7 @@ struct qst_problem {
     qst_precision precision = QST_FP64;
     qst_path path = QST_PATH_KRON;
     qst_param param = QST_PARAM_GAMMA;
+    double alpha = 0.5;           // QST_PARAM_DIRICHLET: concentration of the weights
     std::vector<int64_t> counts;
     std::vector<double> povm_M;   // user POVM: packed measurement matrix (empty: the Pauli settings)
     double* nd = nullptr;  // counts as doubles
@@ -500,7 +516,7 @@ void validate_run(const qst_problem* p, const qst_run_desc& r)
     if (r.pair_every > 0 && r.pair_chains > 0 && (!r.pair_x || !r.pair_ll))
         fail(QST_ERR_INVALID, "pair buffers are NULL");
     if (r.pair_every > 0 && r.surrogate) fail(QST_ERR_UNSUPPORTED, "the pair recorder runs with plain pCN");
-    if (r.surrogate && p->param == QST_PARAM_BURES)
+    if (r.surrogate && p->param != QST_PARAM_GAMMA)
         fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs with the Gaussian/gamma parameterisation");
     if (r.resume) {
         if (!p->have_run) fail(QST_ERR_STATE, "resume requested before any run of this handle");
@@ -540,9 +556,12 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
         p->Q = Q;
         p->D = 1 << Q;
         p->D2 = p->D * p->D;
-        if (desc->param != QST_PARAM_GAMMA && desc->param != QST_PARAM_BURES)
+        if (desc->param != QST_PARAM_GAMMA && desc->param != QST_PARAM_BURES && desc->param != QST_PARAM_DIRICHLET)
             fail(QST_ERR_INVALID, "unknown parameterisation");
+        if (desc->param == QST_PARAM_DIRICHLET && !(desc->alpha > 0.0 && std::isfinite(desc->alpha)))
+            fail(QST_ERR_INVALID, "the Dirichlet concentration alpha must be positive and finite");
         p->param = desc->param;
+        p->alpha = desc->alpha;
         p->d = p->param == QST_PARAM_BURES ? 4 * p->D2 : 2 * p->D2 + p->D;
         p->K = ipow3(Q);
         p->KD = p->K * p->D;
@@ -567,6 +586,8 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
         }
         if (p->param == QST_PARAM_BURES && (p->path != QST_PATH_KRON || Q > 4))
             fail(QST_ERR_UNSUPPORTED, "Algorithm 1 (QST_PARAM_BURES) runs on the Kronecker path, 1..4 qubits");
+        if (p->param == QST_PARAM_DIRICHLET && p->path != QST_PATH_KRON)
+            fail(QST_ERR_UNSUPPORTED, "Dirichlet weights (QST_PARAM_DIRICHLET) run on the Kronecker path");
         if (desc->povm) {
             p->povm_M = povm_matrix_packed(Q, desc->povm, desc->n_povm);
             p->counts.assign(p->KD, 0);
@@ -673,6 +694,8 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
     a.s1 = p->s1;
     a.s2 = p->s2;
     a.n_stored = p->nst;
+    a.alpha = p->alpha;
+    a.lg_alpha = p->param == QST_PARAM_DIRICHLET ? std::lgamma(p->alpha) : 0.0;
     a.n_acc = p->nacc;
     a.n_near = p->nnear;
     a.step_begin = p->step;
@@ -836,7 +859,7 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
             for (int j = 0; j < i; ++j)
                 if (problems[j] == problems[i]) fail(QST_ERR_INVALID, "a handle appears twice in the batch");
             validate_run(problems[i], runs[i]);
-            if (n_problems > 1 && problems[i]->param == QST_PARAM_BURES)
+            if (n_problems > 1 && problems[i]->param != QST_PARAM_GAMMA)
                 fail(QST_ERR_UNSUPPORTED, "batches run the Gaussian/gamma parameterisation");
         }
         DeviceGuard g(dev);
@@ -849,6 +872,8 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
             const qst::ChainArgs a = make_args(p, runs[0]);
             if (p->param == QST_PARAM_BURES)
                 launch_chains_bures(p->Q, static_cast<int>(p->precision), a, s);
+            else if (p->param == QST_PARAM_DIRICHLET)
+                launch_chains_dirichlet(p->Q, static_cast<int>(p->precision), a, s);
             else
                 launch_chains(p->Q, current_shape(p->Q), p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
                               static_cast<int>(p->precision), a, s);

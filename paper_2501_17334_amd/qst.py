@@ -33,12 +33,12 @@ class QstError(RuntimeError):
 class _ProblemDesc(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("counts", C.POINTER(C.c_int64)),
                 ("precision", C.c_int), ("path", C.c_int), ("device", C.c_int32), ("param", C.c_int),
-                ("povm", C.POINTER(C.c_double)), ("n_povm", C.c_int32)]
+                ("povm", C.POINTER(C.c_double)), ("n_povm", C.c_int32), ("alpha", C.c_double)]
 
 
 # parameterisation of rho(x): the Gaussian/gamma form (2D^2+D parameters) or
 # the paper's Algorithm 1, the Bures draw (4D^2 parameters)
-_PARAM = {"gamma": 0, "bures": 1}
+_PARAM = {"gamma": 0, "bures": 1, "dirichlet": 2}
 
 
 class _Surrogate(C.Structure):
@@ -171,9 +171,12 @@ class RunConfig:
 class Problem:
     """A tomography problem on one GPU (qst_init_problem / qst_free_problem)."""
 
-    def __init__(self, n_qubits, counts, precision="fp64", path="auto", device=0, param="gamma", povm=None):
-        """povm: optional [n, D, D] complex POVM elements in place of the Pauli
-        settings (counts then has n entries; dense path, FP64 or FP32)."""
+    def __init__(self, n_qubits, counts, precision="fp64", path="auto", device=0, param="gamma", povm=None,
+                 alpha=0.5):
+        """param: "gamma" (default), "bures" (Algorithm 1) or "dirichlet"
+        (Dirichlet(alpha) weights); povm: optional [n, D, D] complex POVM
+        elements in place of the Pauli settings (counts then has n entries;
+        dense path, FP64 or FP32)."""
         self.Q = int(n_qubits)
         self.D = 2 ** self.Q
         self.K = 3 ** self.Q
@@ -192,7 +195,7 @@ class Problem:
             raise ValueError("counts must have 3^Q * 2^Q entries")
         desc = _ProblemDesc(self.Q, self.counts.ctypes.data_as(C.POINTER(C.c_int64)),
                             _PREC[precision], _PATH[path], device, _PARAM[param],
-                            _f64(self._povm) if self._povm is not None else None, n_povm)
+                            _f64(self._povm) if self._povm is not None else None, n_povm, float(alpha))
         h = C.c_void_p()
         _check(lib().qst_init_problem(C.byref(desc), C.byref(h)))
         self._h = h
