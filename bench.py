@@ -219,6 +219,41 @@ def bures_form(qst, torch, np, prob, cfg, plain_pool):
             "plain_mean_error_to_truth_frobenius": float(np.sqrt(np.sum(np.abs(plain_pool["mean"] - truth) ** 2)))}
 
 
+def option_rates(qst, synth, torch, prob, cfg, steps=1000):
+    """Rates of the other options on the 4-qubit chain count, short runs: the
+    default form with Dirichlet(1) weights (Gamma quantiles by Newton steps),
+    and 81 random measurement bases given as POVM elements (dense path)."""
+    import dataclasses
+    R = cfg.n_chains
+    c = dataclasses.replace(cfg, n_steps=steps, burn_in=0)
+    out = {}
+
+    def timed(P):
+        P.run(dataclasses.replace(c, n_chains=256, n_steps=10), stats=False)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        P.run(c, stats=False)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    P = qst.Problem(prob.n_qubits, prob.counts, param="dirichlet", alpha=1.0)
+    ms = timed(P)
+    out["dirichlet_alpha1"] = {"what": "Dirichlet(1) weights, FP64 Kronecker route, rate only",
+                               "chain_steps_per_s": R * steps / (ms / 1e3), "ms": ms}
+    P.close()
+    bp = synth.random_bases_problem(prob.n_qubits)
+    for prec in ("fp64", "fp32"):
+        P = qst.Problem(prob.n_qubits, bp.counts, precision=prec, povm=bp.povm)
+        ms = timed(P)
+        out[f"povm_random_bases_{prec}"] = {"what": f"81 Haar-random bases as POVM elements, dense MFMA path ({prec}), "
+                                                    "rate only",
+                                            "chain_steps_per_s": R * steps / (ms / 1e3), "ms": ms}
+        P.close()
+    return out
+
+
 def delayed_acceptance(qst, surrogate, synth, torch, np, name="c4", warm=4000, pair_steps=2000, pair_every=20,
                        iters=4000, steps=1000, skill_chains=64, skill_steps=300):
     """Delayed acceptance with the learned surrogate on its own workload (the
@@ -528,6 +563,8 @@ def main():
         if Q <= 4:
             print("[bench] Algorithm 1 (Bures draw)", file=sys.stderr, flush=True)
             out["forms"]["bures"] = bures_form(qst, torch, np, prob, cfg, pool)
+            print("[bench] Dirichlet weights and user POVMs", file=sys.stderr, flush=True)
+            out["forms"].update(option_rates(qst, synth, torch, prob, cfg))
         print("[bench] uneven batch", file=sys.stderr, flush=True)
         out["forms"]["uneven_batch"] = uneven_batch(qst, synth, torch, np)
         if not args.no_delayed:
