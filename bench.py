@@ -436,7 +436,7 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--nsteps", type=int, default=10000)
-    ap.add_argument("--burn-in", type=int, default=2000)
+    ap.add_argument("--burn-in", type=int, default=5000)
     ap.add_argument("--path", default="auto")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

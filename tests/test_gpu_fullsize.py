@@ -1,6 +1,6 @@
 """The 4-qubit benchmark workload at full size, in the launch configuration
 bench.py times: 65536 chains x 10^4 pCN steps in one launch (the tuned team
-shape), burn-in 2000, moments every step, 256 chains recorded every 8 steps.
+shape), burn-in 5000, moments every step, 256 chains recorded every 8 steps.
 
 * Sampled chains (the first four, traced, and the last one) are replayed by
   the oracle over all 10^4 steps: per-step log L within 1e-10 relative and
@@ -29,7 +29,7 @@ def _need_gpu():
 
 def test_fullsize_c3_sampled_chains():
     prob = synth.make_problem("c3")
-    Q, R, NT, burn, beta = 4, prob.n_chains, 10000, 2000, 0.0063
+    Q, R, NT, burn, beta = 4, prob.n_chains, 10000, 5000, 0.0063
     assert R == 65536
     k = 4
     D = 2 ** Q
