@@ -345,11 +345,13 @@ __device__ __forceinline__ double gamma_pq_dev(double a, double t, double lg_a, 
     return pre * h;
 }
 
-// log x of the Gamma(a) quantile at probability Phi(v): Newton steps on
+// log x of the Gamma(a) quantile at probability Phi(v): Halley steps on
 // t = log x for P(a, e^t) = Phi(v) (v <= 0) or Q(a, e^t) = Phi(-v) (v > 0),
-// both increasing in t with derivative x^a e^-x / Gamma(a); started from the
-// Wilson-Hilferty cube (whose normal quantile is v itself) or, where that is
-// not positive, from the leading term of the series.
+// both increasing in t with first derivative g = x^a e^-x / Gamma(a) and
+// g'/g = a - x; started from the Wilson-Hilferty cube (whose normal quantile
+// is v itself) or, where that is not positive, from the leading term of the
+// series or of the tail.  Convergence is cubic: once a step is below 1e-5
+// one more step reaches full precision, and the iteration stops there.
 __device__ __forceinline__ double gamma_quantile_log(double a, double v, double lg_a)
 {
     const double target = 0.5 * erfc((v <= 0.0 ? -v : v) * 0.70710678118654752440);   // Phi(-|v|)
@@ -357,18 +359,22 @@ __device__ __forceinline__ double gamma_quantile_log(double a, double v, double 
     const double wh = 1.0 - c + v * sqrt(c);
     double t = wh > 0.1 ? log(a) + 3.0 * log(wh)
                         : (v <= 0.0 ? (log(target) + lg_a + log(a)) / a : log(a + 1.0) - log(target));
-    for (int it = 0; it < 60; ++it) {
+    bool last = false;
+    for (int it = 0; it < 40; ++it) {
         bool upper;
         const double f = gamma_pq_dev(a, t, lg_a, upper);
         // residual of the increasing function of t: P - u, or (1 - Q) - (1 - q) = q - Q
         double r;
         if (v <= 0.0) r = upper ? (1.0 - f) - target : f - target;
         else r = upper ? target - f : (f - (1.0 - target));
-        const double dens = exp(a * t - exp(t) - lg_a);
-        double step = r / dens;
+        const double x = exp(t);
+        const double newton = r / exp(a * t - x - lg_a);
+        const double corr = 1.0 - 0.5 * newton * (a - x);   // Halley: divide by 1 - f f'' / (2 f'^2)
+        double step = corr > 0.5 ? newton / corr : newton;
         step = fmax(fmin(step, 2.0), -2.0);
         t -= step;
-        if (fabs(step) < 1e-15 * fmax(1.0, fabs(t))) break;
+        if (last) break;
+        last = fabs(step) < 1e-5 * fmax(1.0, fabs(t));
     }
     return t;
 }
