@@ -581,8 +581,8 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
 // ---------------------------------------------------------------------------
 // Algorithm 1 (the Bures draw): rho(x) = W W^dag / Tr(W W^dag), W = (U + I) G
 // ---------------------------------------------------------------------------
-// Sum over the lanes of one matrix column: lane = j + D g, g < G / D (xor
-// masks D, 2D, ..., G/2); every lane of the column gets the same bits.
+// Sum over lanes xor M, 2M, ... below G (the lanes of one matrix column);
+// every lane of the group gets the same bits.
 template <int M, int G>
 __device__ __forceinline__ double column_sum(double v)
 {
@@ -598,7 +598,8 @@ __device__ __forceinline__ double column_sum(double v)
 // factor whose triangular factor has a positive real diagonal: the one that
 // Gram-Schmidt orthonormalisation of H's columns produces, whatever sign
 // convention a Householder QR would take.  Modified Gram-Schmidt across the
-// team: lane j + D g holds rows g + NG r (NG = G / D) of column j; column k is
+// team: lane NG j + g holds rows g + NG r (NG = G / D) of column j, so a
+// column's lanes are neighbours and its sums are quad exchanges; column k is
 // normalised by its own lanes and broadcast through LDS (two alternating
 // buffers of 2D doubles in ubuf), then every later column loses its
 // component along it.  On return the lane holds U's entries of its rows.
@@ -613,7 +614,7 @@ __device__ __forceinline__ void bures_unitary(const double* hbuf, double* ubuf, 
 {
     using BL = BuresLayout<Q, G>;
     constexpr int D = BL::D, D2 = D * D, NG = BL::NG, RPL = BL::RPL;
-    const int j = lane % D, g = lane / D;
+    const int j = lane / NG, g = lane % NG;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int i = g + NG * r;
@@ -628,7 +629,7 @@ __device__ __forceinline__ void bures_unitary(const double* hbuf, double* ubuf, 
         double n2 = 0.0;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) n2 += ar[r] * ar[r] + ai[r] * ai[r];
-        n2 = column_sum<D, G>(n2);
+        n2 = column_sum<1, NG>(n2);
         if (j == k) {
             const double inv = 1.0 / sqrt(n2);
 #pragma unroll
@@ -654,8 +655,8 @@ __device__ __forceinline__ void bures_unitary(const double* hbuf, double* ubuf, 
             cr = __builtin_fma(ur[r], ar[r], __builtin_fma(ui[r], ai[r], cr));
             ci = __builtin_fma(ur[r], ai[r], __builtin_fma(-ui[r], ar[r], ci));
         }
-        cr = column_sum<D, G>(cr);
-        ci = column_sum<D, G>(ci);
+        cr = column_sum<1, NG>(cr);
+        ci = column_sum<1, NG>(ci);
         if (j > k) {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
@@ -682,7 +683,7 @@ __device__ __forceinline__ void stage_rho_bures(const double* ybuf, double* ws, 
     bures_unitary<Q, G>(hbuf, ws, ar, ai, lane);
     team_sync<G>();
     {
-        const int j = lane % D, g = lane / D;
+        const int j = lane / NG, g = lane % NG;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int i = g + NG * r;
