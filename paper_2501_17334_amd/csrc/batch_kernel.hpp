@@ -1,10 +1,18 @@
 // Uneven batches: chains of many problems (1 to 6 qubits, any chain count,
-// FP64 or the FP32 Kronecker form per problem) in ONE persistent launch.  The host cuts every problem into workgroup
-// tiles (WG / G_Q chains each, G_Q the team size of that qubit count), orders
-// the tiles by estimated cost, largest first, and the resident workgroups
-// take tiles from a global counter until the list is exhausted.  A tile runs
-// the same chain_tile code as a single-problem launch, on its own problem's
-// buffers, so a problem's results do not depend on the batch around it.
+// FP64 or the FP32 Kronecker form per problem) in one persistent launch per
+// resource class.  The host cuts every problem into workgroup tiles (WG / G_Q
+// chains each, G_Q the team size of that qubit count), orders the tiles by
+// estimated cost, largest first, and the resident workgroups take tiles from a
+// global counter until the list is exhausted.  A tile runs the same chain_tile
+// code as a single-problem launch, on its own problem's buffers, so a
+// problem's results do not depend on the batch around it.
+//
+// A launch's register and LDS allocation is that of its largest tile.  The
+// 6-qubit tiles need 256 VGPRs and about 150 KB of LDS, which leaves room for
+// one 512-thread workgroup per CU (two wavefronts per SIMD); tiles of up to 5
+// qubits fit in 128 VGPRs, i.e. twice the resident wavefronts.  So the 6-qubit tiles form one launch (k_chains_batch<6>, 512-
+// thread workgroups) and all smaller tiles another (k_chains_batch<5>,
+// 256-thread workgroups), back to back on the stream.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,7 +22,12 @@
 
 namespace qst {
 
-constexpr int kBatchWG = 512;
+// Workgroup size of each launch class: 512 threads for the 6-qubit tiles
+// (one 512-thread team), 256 for tiles of up to 5 qubits, so that a 5-qubit
+// tile is one 256-thread team with barriers of its own, as in its
+// single-problem launch.
+constexpr int batch_wg(int qmax) { return qmax == 6 ? 512 : 256; }
+constexpr int batch_class(int q) { return q == 6 ? 6 : 5; }
 
 struct BatchItem {
     int32_t problem;   // index into the ChainArgs array
@@ -40,7 +53,7 @@ struct BatchTeam {
 template <int Q>
 constexpr size_t batch_lds_doubles()
 {
-    return static_cast<size_t>(kBatchWG / BatchTeam<Q>::G) * TeamShape<Q, BatchTeam<Q>::G>::kLdsChain +
+    return static_cast<size_t>(batch_wg(batch_class(Q)) / BatchTeam<Q>::G) * TeamShape<Q, BatchTeam<Q>::G>::kLdsChain +
            WgTables<Q>::kDoubles;
 }
 
@@ -49,30 +62,45 @@ constexpr size_t batch_lds_doubles()
 // with all six chain steps inlined into one body the kernel needed long
 // branches and heavy register spilling, and its 5-qubit tiles computed wrong
 // likelihoods.
-template <int Q, int PREC>
+template <int Q, int PREC, int QMAX>
 __device__ __attribute__((noinline)) void batch_tile(const ChainArgs& A, int64_t chain0)
 {
     extern __shared__ double batch_lds[];
-    wg_tables_init<Q>(batch_lds, threadIdx.x, kBatchWG);
+    static_assert(batch_class(Q) == QMAX, "a tile runs in the launch of its class");
+    constexpr int WG = batch_wg(QMAX);
+    wg_tables_init<Q>(batch_lds, threadIdx.x, WG);
     __syncthreads();
-    chain_tile<Q, BatchTeam<Q>::G, kBatchWG, kPathKron, PREC>(A, chain0, batch_lds,
+    chain_tile<Q, BatchTeam<Q>::G, WG, kPathKron, PREC>(A, chain0, batch_lds,
                                                               batch_lds + WgTables<Q>::kDoubles);
 }
 
-template <int PREC>
+// Tiles of QMAX = 5 (qubit counts 1..5) or QMAX = 6 (6 qubits only).  The
+// host sorts every tile into the launch of its class; a tile of the other
+// class is left alone here rather than run with the wrong sizes.
+template <int PREC, int QMAX>
 __device__ __forceinline__ void batch_dispatch(int q, const ChainArgs& A, int64_t chain0)
 {
-    switch (q) {
-        case 1: batch_tile<1, PREC>(A, chain0); break;
-        case 2: batch_tile<2, PREC>(A, chain0); break;
-        case 3: batch_tile<3, PREC>(A, chain0); break;
-        case 4: batch_tile<4, PREC>(A, chain0); break;
-        case 5: batch_tile<5, PREC>(A, chain0); break;
-        default: batch_tile<6, PREC>(A, chain0); break;
+    if constexpr (QMAX == 6) {
+        if (q == 6) batch_tile<6, PREC, 6>(A, chain0);
+    } else {
+        switch (q) {
+            case 1: batch_tile<1, PREC, 5>(A, chain0); break;
+            case 2: batch_tile<2, PREC, 5>(A, chain0); break;
+            case 3: batch_tile<3, PREC, 5>(A, chain0); break;
+            case 4: batch_tile<4, PREC, 5>(A, chain0); break;
+            case 5: batch_tile<5, PREC, 5>(A, chain0); break;
+            default: break;
+        }
     }
 }
 
-__global__ __launch_bounds__(kBatchWG, 2) void k_chains_batch(BatchArgs B)
+// Wavefronts per SIMD the launch is compiled for: 4 (128 VGPRs) for tiles of
+// up to 5 qubits, 2 (256 VGPRs) for 6-qubit tiles.
+template <int QMAX>
+constexpr int batch_waves_per_simd() { return QMAX == 6 ? 2 : 4; }
+
+template <int QMAX>
+__global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void k_chains_batch(BatchArgs B)
 {
     __shared__ int32_t take;
     for (;;) {
@@ -83,8 +111,8 @@ __global__ __launch_bounds__(kBatchWG, 2) void k_chains_batch(BatchArgs B)
         if (it >= B.n_items) break;
         const BatchItem I = B.items[it];
         const ChainArgs A = B.problems[I.problem];
-        if (I.prec == kPrecF32) batch_dispatch<kPrecF32>(I.q, A, I.chain0);
-        else batch_dispatch<kPrecF64>(I.q, A, I.chain0);
+        if (I.prec == kPrecF32) batch_dispatch<kPrecF32, QMAX>(I.q, A, I.chain0);
+        else batch_dispatch<kPrecF64, QMAX>(I.q, A, I.chain0);
         __syncthreads();
     }
 }

@@ -781,57 +781,70 @@ double chain_step_cost(int Q)
     return c[Q];
 }
 
+// One persistent launch per resource class (6-qubit tiles, then tiles of up
+// to 5 qubits), each over its own largest-first tile list and counter.
+template <int QMAX>
+void launch_batch_class(const std::vector<qst::BatchItem>& sorted, size_t lds, const qst::ChainArgs* dargs,
+                        qst::BatchItem* ditems, int32_t* counter, hipStream_t s)
+{
+    if (sorted.empty()) return;
+    if (sorted.size() > 0x7fffffff) fail(QST_ERR_INVALID, "batch too large");
+    hip_check(hipMemcpy(ditems, sorted.data(), sizeof(qst::BatchItem) * sorted.size(), hipMemcpyHostToDevice),
+              "copy batch tiles");
+    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_batch<QMAX>), lds);
+    int dev = 0, n_cu = 0, per_cu = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qst::k_chains_batch<QMAX>, qst::batch_wg(QMAX), lds),
+              "occupancy");
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(sorted.size()),
+                                                                 static_cast<int64_t>(n_cu) * std::max(per_cu, 1)));
+    hipLaunchKernelGGL(qst::k_zero_counter, dim3(1), dim3(1), 0, s, counter);
+    hip_check(hipGetLastError(), "counter reset");
+    qst::BatchArgs b{dargs, ditems, static_cast<int32_t>(sorted.size()), counter};
+    hipLaunchKernelGGL(qst::k_chains_batch<QMAX>, dim3(static_cast<unsigned>(grid)), dim3(qst::batch_wg(QMAX)), lds, s, b);
+    hip_check(hipGetLastError(), "batch kernel launch");
+    // the tile list and the counter are reused by the next class
+    hip_check(hipStreamSynchronize(s), "batch synchronize");
+}
+
 void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* runs, hipStream_t s)
 {
     std::vector<qst::ChainArgs> args(n);
     std::vector<qst::BatchItem> items;
     std::vector<double> cost;
-    size_t lds = 0;
+    size_t lds_small = 0, lds_big = 0;   // tiles of 1..5 qubits; 6-qubit tiles
     for (int i = 0; i < n; ++i) {
         qst_problem* p = problems[i];
         if (p->path != QST_PATH_KRON)
             fail(QST_ERR_UNSUPPORTED, "batched launches use the Kronecker path (FP64 or FP32)");
         args[i] = make_args(p, runs[i]);
-        const int per = qst::kBatchWG / batch_team(p->Q);
+        const int per = qst::batch_wg(qst::batch_class(p->Q)) / batch_team(p->Q);
         const int32_t prec = p->precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64;
         for (int64_t c0 = 0; c0 < p->R; c0 += per) {
             items.push_back({i, p->Q, c0, prec, 0});
             cost.push_back(chain_step_cost(p->Q) * static_cast<double>(std::min<int64_t>(per, p->R - c0)) *
                            static_cast<double>(std::max<int64_t>(runs[i].n_steps, 1)));
         }
-        lds = std::max(lds, batch_lds_bytes(p->Q));
+        size_t& l = p->Q == 6 ? lds_big : lds_small;
+        l = std::max(l, batch_lds_bytes(p->Q));
     }
     std::vector<size_t> order(items.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<qst::BatchItem> sorted(items.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
-    if (sorted.size() > 0x7fffffff) fail(QST_ERR_INVALID, "batch too large");
+    std::vector<qst::BatchItem> small, big;
+    for (size_t i : order) (items[i].q == 6 ? big : small).push_back(items[i]);
 
     qst::ChainArgs* dargs = dev_alloc<qst::ChainArgs>(args.size());
     qst::BatchItem* ditems = nullptr;
     int32_t* counter = nullptr;
     try {
-        ditems = dev_alloc<qst::BatchItem>(sorted.size());
+        ditems = dev_alloc<qst::BatchItem>(std::max<size_t>(1, std::max(small.size(), big.size())));
         counter = dev_alloc<int32_t>(1);
         hip_check(hipMemcpy(dargs, args.data(), sizeof(qst::ChainArgs) * args.size(), hipMemcpyHostToDevice),
                   "copy batch problems");
-        hip_check(hipMemcpy(ditems, sorted.data(), sizeof(qst::BatchItem) * sorted.size(), hipMemcpyHostToDevice),
-                  "copy batch tiles");
-        allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_batch), lds);
-        int dev = 0, n_cu = 0, per_cu = 0;
-        hip_check(hipGetDevice(&dev), "hipGetDevice");
-        hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
-        hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qst::k_chains_batch, qst::kBatchWG, lds),
-                  "occupancy");
-        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(sorted.size()),
-                                                                     static_cast<int64_t>(n_cu) * std::max(per_cu, 1)));
-        hipLaunchKernelGGL(qst::k_zero_counter, dim3(1), dim3(1), 0, s, counter);
-        hip_check(hipGetLastError(), "counter reset");
-        qst::BatchArgs b{dargs, ditems, static_cast<int32_t>(sorted.size()), counter};
-        hipLaunchKernelGGL(qst::k_chains_batch, dim3(static_cast<unsigned>(grid)), dim3(qst::kBatchWG), lds, s, b);
-        hip_check(hipGetLastError(), "batch kernel launch");
-        hip_check(hipStreamSynchronize(s), "batch synchronize");
+        launch_batch_class<6>(big, lds_big, dargs, ditems, counter, s);
+        launch_batch_class<5>(small, lds_small, dargs, ditems, counter, s);
     } catch (...) {
         dev_free(dargs);
         dev_free(ditems);

@@ -400,7 +400,8 @@ def list_launch_shapes(n_qubits):
 
 
 def run_batch(problems, configs, stats=True, stream=None, traces=None):
-    """qst_run_chains on several problems in one launch (the uneven batch).
+    """qst_run_chains on several problems at once (the uneven batch: one
+    work-queue launch for 6-qubit problems, one for all smaller ones).
     traces: optional list (one entry per problem, None or a trace dict as in
     Problem.run)."""
     n = len(problems)

@@ -1,4 +1,5 @@
-"""Uneven batches in one persistent launch, and the launch-shape tuner.
+"""Uneven batches (persistent work-queue launches: 6-qubit tiles, then all
+smaller ones), and the launch-shape tuner.
 
 A batch of problems of 1..6 qubits must give each problem exactly (bit for
 bit) what running it alone gives with the same team size, because every
