@@ -59,6 +59,34 @@ def flops_per_chain_step_bures(Q, stored_fraction):
     return proposal + qr + w + trace + rho + contraction + loglik + moments
 
 
+def flops_per_chain_step_dense(Q, stored_fraction, rows=None):
+    """Algorithmic flops of one chain-step on the dense path: the default
+    parameterisation's proposal, weights, rho and moments, the contraction
+    p = M vec rho as a dense product over the D^2 packed reals of rho for each
+    of the rows of M (K D Pauli projectors, or the user's POVM elements), and
+    the count-weighted log sum.  Returns (total, contraction)."""
+    D = 2 ** Q
+    rows = 6 ** Q if rows is None else rows
+    d = 2 * D * D + D
+    contraction = 2 * rows * D * D
+    rest = 2 * d + 4 * D * D + 3 * D + 4 * D ** 3 + 2 * rows + 3 * D * D * stored_fraction
+    return contraction + rest, contraction
+
+
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+
+
+def dense_rate_entry(what, R, steps, ms, Q, prec, rows=None):
+    """Rate of a dense-path run with the achieved rate of its contraction
+    flops against the MFMA peak of the contraction's precision (BF16x3: the
+    algorithmic flops of the product, against the BF16 peak)."""
+    total, con = flops_per_chain_step_dense(Q, 1.0, rows)
+    rate = R * steps / (ms / 1e3)
+    return {"what": what, "chain_steps_per_s": rate, "ms": ms, "flop_per_chain_step": total,
+            "contraction_flop_per_chain_step": con, "contraction_tflops": rate * con / 1e12,
+            "mfma_peak_tflops": MFMA_PEAK_TFLOPS[prec], "frac_mfma_peak": rate * con / 1e12 / MFMA_PEAK_TFLOPS[prec]}
+
+
 def kernel_source_hash():
     """Hash of the code the chain kernel is compiled from (its device code:
     the step, the random numbers, the fast math), comments and blank space
@@ -177,9 +205,9 @@ def chosen_forms(qst, torch, np, prob, cfg, record, plain_pool, plain_ms, plain_
             P = qst.Problem(Q, prob.counts, precision=prec, path="dense")
             c2 = dataclasses.replace(cfg, n_steps=dense_steps, burn_in=0)
             ms = timed(P, c2, None)
-            out[f"dense_{prec}"] = {"what": f"dense MFMA contraction in the chain kernel ({prec}), "
-                                            f"{dense_steps}-step run, rate only",
-                                    "chain_steps_per_s": R * dense_steps / (ms / 1e3), "ms": ms}
+            out[f"dense_{prec}"] = dense_rate_entry(f"dense MFMA contraction in the chain kernel ({prec}), "
+                                                    f"{dense_steps}-step run, moments every step", R, dense_steps,
+                                                    ms, Q, prec)
             P.close()
     return out
 
@@ -247,9 +275,9 @@ def option_rates(qst, synth, torch, prob, cfg, steps=1000):
     for prec in ("fp64", "fp32"):
         P = qst.Problem(prob.n_qubits, bp.counts, precision=prec, povm=bp.povm)
         ms = timed(P)
-        out[f"povm_random_bases_{prec}"] = {"what": f"81 Haar-random bases as POVM elements, dense MFMA path ({prec}), "
-                                                    "rate only",
-                                            "chain_steps_per_s": R * steps / (ms / 1e3), "ms": ms}
+        out[f"povm_random_bases_{prec}"] = dense_rate_entry(
+            f"81 Haar-random bases as POVM elements, dense MFMA path ({prec}), {steps}-step run, moments every step",
+            R, steps, ms, prob.n_qubits, prec, rows=bp.povm.shape[0])
         P.close()
     return out
 
