@@ -44,6 +44,14 @@
  * boundary.  On failure, outputs are unspecified and qst_last_error() gives
  * a message (thread-local, valid until the next call on the same thread).
  * Handles are not thread-safe.
+ *
+ * Caller-owned device buffers (traces, records, training pairs, states and
+ * outputs of qst_loglik, qst_acf and the MLP calls) are checked before any
+ * kernel is launched: a buffer that is not device memory of the handle's
+ * device (or, without a handle, of the current device), or whose allocation
+ * ends before the last byte the call would touch, gives QST_ERR_INVALID.
+ * A buffer carved from a larger allocation is only checked against the end
+ * of that allocation.
  */
 #ifndef QST_H
 #define QST_H

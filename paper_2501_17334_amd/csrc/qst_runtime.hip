@@ -40,6 +40,40 @@ void hip_check(hipError_t e, const char* what)
     if (e != hipSuccess) fail(QST_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// A caller-owned device buffer: device memory of `device` with at least
+// `bytes` bytes from p to the end of its allocation (an allocator may hand
+// out part of a larger allocation, so a buffer that is too small but lies
+// inside a larger block passes; host memory, another device's memory and
+// overruns past the allocation are refused).
+void check_device_buffer(const void* p, size_t bytes, int device, const char* what)
+{
+    if (bytes == 0) return;
+    if (!p) fail(QST_ERR_INVALID, std::string(what) + " is NULL");
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(QST_ERR_INVALID, std::string(what) + " is not device memory");
+    }
+    if (at.type != hipMemoryTypeDevice) fail(QST_ERR_INVALID, std::string(what) + " is not device memory");
+    if (at.device != device) fail(QST_ERR_INVALID, std::string(what) + " is on another device");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(QST_ERR_INVALID, std::string(what) + ": allocation not found");
+    }
+    const size_t off = static_cast<size_t>(static_cast<const char*>(p) - static_cast<const char*>(base));
+    if (off > size || bytes > size - off)
+        fail(QST_ERR_INVALID, std::string(what) + " is smaller than the call needs");
+}
+
+int current_device()
+{
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    return dev;
+}
+
 // Dynamic LDS above the default limit must be allowed per kernel and per
 // device once; a larger request later raises the allowance.
 void allow_dynamic_lds(const void* kernel, size_t bytes)
@@ -518,6 +552,24 @@ void validate_run(const qst_problem* p, const qst_run_desc& r)
     if (r.pair_every > 0 && r.surrogate) fail(QST_ERR_UNSUPPORTED, "the pair recorder runs with plain pCN");
     if (r.surrogate && p->param != QST_PARAM_GAMMA)
         fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs with the Gaussian/gamma parameterisation");
+    // extents of what the kernels write into the caller's buffers
+    const size_t steps = static_cast<size_t>(r.n_steps);
+    const size_t tc = static_cast<size_t>(std::min<int64_t>(r.trace_chains, r.n_chains));
+    if (r.trace_llprop) check_device_buffer(r.trace_llprop, tc * steps * sizeof(double), p->device, "trace_llprop");
+    if (r.trace_logu) check_device_buffer(r.trace_logu, tc * steps * sizeof(double), p->device, "trace_logu");
+    if (r.trace_accept) check_device_buffer(r.trace_accept, tc * steps, p->device, "trace_accept");
+    if (r.record_every > 0 && r.record_chains > 0) {
+        const size_t rc = static_cast<size_t>(std::min<int64_t>(r.record_chains, r.n_chains));
+        check_device_buffer(r.record_buf, rc * (steps / r.record_every) * p->D2 * sizeof(double), p->device,
+                            "record_buf");
+    }
+    if (r.pair_every > 0 && r.pair_chains > 0) {
+        const size_t slots = steps / r.pair_every;
+        const size_t pc = static_cast<size_t>(r.pair_chains);
+        const size_t rows = slots > 0 ? (slots - 1) * pc + std::min<size_t>(pc, static_cast<size_t>(r.n_chains)) : 0;
+        check_device_buffer(r.pair_x, rows * p->da_width() * sizeof(uint16_t), p->device, "pair_x");
+        check_device_buffer(r.pair_ll, rows * sizeof(double), p->device, "pair_ll");
+    }
     if (r.resume) {
         if (!p->have_run) fail(QST_ERR_STATE, "resume requested before any run of this handle");
         if (r.n_chains != p->R) fail(QST_ERR_INVALID, "resume with a different n_chains");
@@ -1040,6 +1092,8 @@ qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double
         if (n < 0) fail(QST_ERR_INVALID, "negative n");
         if (n == 0) return;
         if (!rho || !ll_out) fail(QST_ERR_INVALID, "NULL buffer");
+        check_device_buffer(rho, static_cast<size_t>(n) * p->D2 * 2 * sizeof(double), p->device, "rho");
+        check_device_buffer(ll_out, static_cast<size_t>(n) * sizeof(double), p->device, "ll_out");
         const qst_path pth = path == QST_PATH_AUTO ? p->path : path;
         if (pth == QST_PATH_KRON && !p->povm_M.empty())
             fail(QST_ERR_UNSUPPORTED, "user POVMs need the dense path");
@@ -1069,6 +1123,8 @@ qst_status qst_acf(const double* records, int64_t n_chains, int64_t n_samples, i
         if (n_chains < 1 || l_max < 0 || n_samples <= l_max)
             fail(QST_ERR_INVALID, "need n_chains >= 1 and n_samples > l_max >= 0");
         if (n_chains > 65535) fail(QST_ERR_INVALID, "at most 65535 recorded chains");
+        check_device_buffer(records, static_cast<size_t>(n_chains) * n_samples * (size_t(1) << (2 * n_qubits)) *
+                                         sizeof(double), current_device(), "records");
         hipStream_t s = static_cast<hipStream_t>(stream);
         const int D = 1 << n_qubits;
         double* part = dev_alloc<double>(static_cast<size_t>(n_chains) * (l_max + 1));
@@ -1244,6 +1300,14 @@ void check_mlp_batch(const qst_mlp* h, int64_t n)
     if (n > (1 << 24)) fail(QST_ERR_INVALID, "batch too large");
 }
 
+// x: [n, d] BF16 rows, y: [n] FP32 targets (y may be NULL where none is read)
+void check_mlp_inputs(const qst_mlp* h, const uint16_t* x, const float* y, int64_t n, bool need_y = true)
+{
+    if (!x || (need_y && !y)) fail(QST_ERR_INVALID, "NULL batch");
+    check_device_buffer(x, static_cast<size_t>(n) * h->d * sizeof(uint16_t), h->device, "x");
+    if (y) check_device_buffer(y, static_cast<size_t>(n) * sizeof(float), h->device, "y");
+}
+
 }  // namespace
 
 extern "C" {
@@ -1332,7 +1396,7 @@ qst_status qst_mlp_gradients(qst_mlp* h, const uint16_t* x, const float* y, int6
 {
     return guarded([&] {
         check_mlp_batch(h, n);
-        if (!x || !y) fail(QST_ERR_INVALID, "NULL batch");
+        check_mlp_inputs(h, x, y, n);
         DeviceGuard g(h->device);
         hipStream_t s = static_cast<hipStream_t>(stream);
         mlp_forward(h, x, n, nullptr, y, s);
@@ -1353,7 +1417,7 @@ qst_status qst_mlp_train_step(qst_mlp* h, const uint16_t* x, const float* y, int
 {
     return guarded([&] {
         check_mlp_batch(h, n);
-        if (!x || !y) fail(QST_ERR_INVALID, "NULL batch");
+        check_mlp_inputs(h, x, y, n);
         if (!(lr > 0.0f)) fail(QST_ERR_INVALID, "learning rate must be positive");
         DeviceGuard g(h->device);
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1381,6 +1445,8 @@ qst_status qst_mlp_predict(qst_mlp* h, const uint16_t* x, int64_t n, float* out,
     return guarded([&] {
         if (!h || !x || !out) fail(QST_ERR_INVALID, "NULL argument");
         if (n < 1) fail(QST_ERR_INVALID, "empty batch");
+        check_mlp_inputs(h, x, nullptr, n, false);
+        check_device_buffer(out, static_cast<size_t>(n) * sizeof(float), h->device, "out");
         DeviceGuard g(h->device);
         mlp_forward(h, x, n, out, nullptr, static_cast<hipStream_t>(stream));
     });
@@ -1391,6 +1457,9 @@ qst_status qst_mlp_targets(const double* ll, int64_t n, float* y, double* mean, 
     return guarded([&] {
         if (!ll || !y || !mean || !sd) fail(QST_ERR_INVALID, "NULL argument");
         if (n < 2) fail(QST_ERR_INVALID, "need at least two targets");
+        const int dev = current_device();
+        check_device_buffer(ll, static_cast<size_t>(n) * sizeof(double), dev, "ll");
+        check_device_buffer(y, static_cast<size_t>(n) * sizeof(float), dev, "y");
         hipStream_t s = static_cast<hipStream_t>(stream);
         double* mom = dev_alloc<double>(3);
         double host[3] = {0.0, 0.0, 0.0};
@@ -1422,6 +1491,13 @@ qst_status qst_gather_rows(const uint16_t* x, int32_t width, const float* y, con
         if (n < 0 || width < 1) fail(QST_ERR_INVALID, "bad sizes");
         if (n == 0) return;
         if (n > 0x7fffffff) fail(QST_ERR_INVALID, "too many rows");
+        // the source rows are those idx names; only their memory type is checked
+        const int dev = current_device();
+        check_device_buffer(x, static_cast<size_t>(width) * sizeof(uint16_t), dev, "x");
+        check_device_buffer(y, sizeof(float), dev, "y");
+        check_device_buffer(idx, static_cast<size_t>(n) * sizeof(int64_t), dev, "idx");
+        check_device_buffer(xo, static_cast<size_t>(n) * width * sizeof(uint16_t), dev, "xo");
+        check_device_buffer(yo, static_cast<size_t>(n) * sizeof(float), dev, "yo");
         hipLaunchKernelGGL(qst::k_gather_rows, dim3(static_cast<unsigned>(n)), dim3(256), 0,
                            static_cast<hipStream_t>(stream), x, width, y, idx, n, xo, yo);
         hip_check(hipGetLastError(), "gather launch");

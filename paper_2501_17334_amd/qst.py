@@ -143,6 +143,31 @@ def _dptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _dev_tensor(t, dtypes, name):
+    """A torch tensor the library reads or writes through a raw pointer: on
+    a GPU, contiguous, of one of the given dtype names (the library checks
+    the memory type and the extent of the allocation itself)."""
+    import torch
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise QstError(QST_ERR_INVALID, f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise QstError(QST_ERR_INVALID, f"{name} must be contiguous")
+    if str(t.dtype).replace("torch.", "") not in dtypes:
+        raise QstError(QST_ERR_INVALID, f"{name} must have dtype {' or '.join(dtypes)}, not {t.dtype}")
+
+
+def _check_run_buffers(trace, record, pairs):
+    trace, record, pairs = trace or {}, record or {}, pairs or {}
+    _dev_tensor(trace.get("llprop"), ("float64",), "trace llprop")
+    _dev_tensor(trace.get("logu"), ("float64",), "trace logu")
+    _dev_tensor(trace.get("accept"), ("int8", "uint8"), "trace accept")
+    _dev_tensor(record.get("buf"), ("float64",), "record buf")
+    _dev_tensor(pairs.get("x"), ("bfloat16", "int16", "uint16"), "pairs x")
+    _dev_tensor(pairs.get("ll"), ("float64",), "pairs ll")
+
+
 def _f64(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
@@ -239,6 +264,7 @@ class Problem:
         chains=, x= bfloat16 [n_steps // every, chains, pair_width], ll= float64
         [n_steps // every, chains]): the proposal of step (s + 1) * every of
         chain c and its log L in row s * chains + c."""
+        _check_run_buffers(trace, record, pairs)
         rd = self._run_desc(cfg, trace, record, stream, surrogate, pairs)
         arr = (C.c_void_p * 1)(self._h)
         st = _RunStats()
@@ -287,6 +313,8 @@ class Problem:
     def loglik(self, rho_dev, out_dev, path="auto", precision="fp64", stream=None):
         """qst_loglik on torch device tensors: rho [n, D, D] complex128 (or
         float64 [n, D, D, 2]), out float64 [n]."""
+        _dev_tensor(rho_dev, ("complex128", "float64"), "rho")
+        _dev_tensor(out_dev, ("float64",), "out")
         n = out_dev.numel()
         _check(lib().qst_loglik(self._h, C.c_void_p(rho_dev.data_ptr()), n, C.c_void_p(out_dev.data_ptr()),
                                 _PATH[path], _PREC[precision],
@@ -343,6 +371,8 @@ class Mlp:
     def train_step(self, x_bf16, y_f32, lr, want_loss=False, rows=None, offset=0):
         """One Adam step on rows [offset, offset + rows) of device tensors
         x_bf16 [N, d] (bfloat16) and y_f32 [N] (pointer arithmetic only)."""
+        _dev_tensor(x_bf16, ("bfloat16",), "x")
+        _dev_tensor(y_f32, ("float32",), "y")
         n = x_bf16.shape[0] if rows is None else rows
         xp = x_bf16.data_ptr() + offset * x_bf16.shape[1] * 2
         yp = y_f32.data_ptr() + offset * 4
@@ -367,6 +397,8 @@ class Mlp:
 
 def standardise_targets(ll_dev, y_dev, stream=None):
     """qst_mlp_targets: y = (ll - mean) / sd on the device; returns (mean, sd)."""
+    _dev_tensor(ll_dev, ("float64",), "ll")
+    _dev_tensor(y_dev, ("float32",), "y")
     mean, sd = C.c_double(), C.c_double()
     _check(lib().qst_mlp_targets(C.c_void_p(ll_dev.data_ptr()), ll_dev.numel(), C.c_void_p(y_dev.data_ptr()),
                                  C.byref(mean), C.byref(sd), stream if stream is not None else current_stream()))
@@ -375,6 +407,9 @@ def standardise_targets(ll_dev, y_dev, stream=None):
 
 def gather_rows(x, y, idx, xo, yo, stream=None):
     """qst_gather_rows on torch device tensors (idx int64)."""
+    for t, dt, name in ((x, ("bfloat16",), "x"), (y, ("float32",), "y"), (idx, ("int64",), "idx"),
+                        (xo, ("bfloat16",), "xo"), (yo, ("float32",), "yo")):
+        _dev_tensor(t, dt, name)
     _check(lib().qst_gather_rows(C.c_void_p(x.data_ptr()), x.shape[1], C.c_void_p(y.data_ptr()),
                                  C.c_void_p(idx.data_ptr()), idx.numel(), C.c_void_p(xo.data_ptr()),
                                  C.c_void_p(yo.data_ptr()), stream if stream is not None else current_stream()))
@@ -406,6 +441,8 @@ def run_batch(problems, configs, stats=True, stream=None, traces=None):
     Problem.run)."""
     n = len(problems)
     traces = traces or [None] * n
+    for t in traces:
+        _check_run_buffers(t, None, None)
     rds = (_RunDesc * n)(*[p._run_desc(c, t, None, stream) for p, c, t in zip(problems, configs, traces)])
     hs = (C.c_void_p * n)(*[p._h for p in problems])
     st = (_RunStats * n)()
@@ -420,6 +457,7 @@ def run_batch(problems, configs, stats=True, stream=None, traces=None):
 def acf(records_dev, l_max=200, stream=None):
     """qst_acf: pooled c[0..l_max] (Eq. (ACFrho)) of recorded packed samples,
     a torch device tensor [chains, N, D, D] float64."""
+    _dev_tensor(records_dev, ("float64",), "records")
     C_, N, D, _ = records_dev.shape
     Q = int(D).bit_length() - 1
     out = np.zeros(l_max + 1)

@@ -50,3 +50,19 @@ def test_null_arguments_are_invalid():
     assert qst.lib().qst_init_problem(None, ctypes.byref(h)) == qst.QST_ERR_INVALID
     assert qst.lib().qst_pool_moments(None, None, None, None, None) == qst.QST_ERR_INVALID
     assert qst.lib().qst_run_chains(None, 0, None, None) == qst.QST_ERR_INVALID
+
+
+def test_binding_refuses_host_and_strided_tensors():
+    """Tensors handed to the library as raw pointers must be contiguous GPU
+    tensors of the documented dtype; the binding refuses anything else before
+    any library call."""
+    import torch
+    with pytest.raises(qst.QstError) as e:
+        qst._dev_tensor(torch.zeros(4, dtype=torch.float64), ("float64",), "buf")
+    assert e.value.status == qst.QST_ERR_INVALID and "GPU tensor" in str(e.value)
+    with pytest.raises(qst.QstError):
+        qst._dev_tensor(np.zeros(4), ("float64",), "buf")
+    with pytest.raises(qst.QstError):
+        qst._check_run_buffers(dict(chains=1, llprop=torch.zeros((1, 4), dtype=torch.float64)), None, None)
+    qst._dev_tensor(None, ("float64",), "buf")          # absent buffers are allowed
+    qst._check_run_buffers(None, None, None)
