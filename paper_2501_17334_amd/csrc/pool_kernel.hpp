@@ -24,6 +24,9 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool_partial(const double* __r
     const int64_t r1 = r0 + chunk < R ? r0 + chunk : R;
     for (int i = threadIdx.x; i < D2; i += blockDim.x) {
         double a = 0.0, b = 0.0, m = 0.0, mm = 0.0, cnt = 0.0;
+        // unrolled so that the loads of several chains are in flight at
+        // once; every sum still runs over the chains in index order
+#pragma unroll 8
         for (int64_t r = r0; r < r1; ++r) {
             const double x1 = s1[r * D2 + i];
             a += x1;
@@ -51,7 +54,8 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool_partial(const double* __r
 }
 
 // out layout (doubles): mean [D2*2] interleaved complex, second [D2*2]
-// (E[(Re a)^2], E[(Im a)^2]), se [D2*2]; nout[0] = total samples.
+// (E[(Re a)^2], E[(Im a)^2]), se [D2*2]; nout[0] = total samples.  One
+// thread per matrix element, ceil(D2 / kPoolThreads) workgroups.
 __global__ __launch_bounds__(kPoolThreads) void k_pool_final(const double* __restrict__ part,
                                                              const int64_t* __restrict__ nsum,
                                                              int nchunks, int D, double* out,
@@ -63,22 +67,27 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool_final(const double* __res
         int64_t n = 0;
         for (int c = 0; c < nchunks; ++c) n += nsum[c];
         ntot_s = n;
-        nout[0] = n;
+        if (blockIdx.x == 0) nout[0] = n;
     }
     __syncthreads();
     const double ntot = static_cast<double>(ntot_s);
-    for (int p = threadIdx.x; p < D2; p += blockDim.x) {
+    const int p = static_cast<int>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p < D2) {
         const int a = p / D, b = p % D;
         const int up = (a <= b) ? a * D + b : b * D + a;   // packed slot of Re rho_ab
         const int lo = (a <= b) ? b * D + a : a * D + b;   // packed slot of Im of the upper element
-        double sums[2][5];
+        double sums[2][5] = {};
         const int slots[2] = {up, lo};
-        for (int s = 0; s < 2; ++s)
-            for (int k = 0; k < 5; ++k) {
-                double acc = 0.0;
-                for (int c = 0; c < nchunks; ++c) acc += part[(static_cast<int64_t>(c) * 5 + k) * D2 + slots[s]];
-                sums[s][k] = acc;
-            }
+        // the ten sums side by side (their loads overlap), each over the
+        // chunks in index order
+#pragma unroll 4
+        for (int c = 0; c < nchunks; ++c) {
+            const double* pc = part + static_cast<int64_t>(c) * 5 * D2;
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int k = 0; k < 5; ++k) sums[s][k] += pc[k * D2 + slots[s]];
+        }
         const double im_sign = (a < b) ? 1.0 : -1.0;
         const bool diag = (a == b);
         // mean

@@ -1029,8 +1029,8 @@ qst_status qst_pool_moments(const qst_problem* p, double* mean, double* second, 
             hipLaunchKernelGGL(qst::k_pool_partial, dim3(nchunks), dim3(qst::kPoolThreads), 0, s, p->s1, p->s2,
                                p->nst, p->R, p->D2, chunk, part, nsum);
             hip_check(hipGetLastError(), "pool partial launch");
-            hipLaunchKernelGGL(qst::k_pool_final, dim3(1), dim3(qst::kPoolThreads), 0, s, part, nsum, nchunks, p->D,
-                               outd, nout);
+            hipLaunchKernelGGL(qst::k_pool_final, dim3((p->D2 + qst::kPoolThreads - 1) / qst::kPoolThreads),
+                               dim3(qst::kPoolThreads), 0, s, part, nsum, nchunks, p->D, outd, nout);
             hip_check(hipGetLastError(), "pool final launch");
             std::vector<double> host(static_cast<size_t>(6) * p->D2);
             int64_t ntot = 0;
