@@ -1,6 +1,6 @@
 // Uneven batches: chains of many problems (1 to 6 qubits, any chain count,
 // FP64 or the FP32 Kronecker form per problem) in one persistent launch per
-// resource class.  The host cuts every problem into workgroup tiles (WG / G_Q
+// launch class.  The host cuts every problem into workgroup tiles (WG / G_Q
 // chains each, G_Q the team size of that qubit count), orders the tiles by
 // estimated cost, largest first, and the resident workgroups take tiles from a
 // global counter until the list is exhausted.  A tile runs the same chain_tile
@@ -10,9 +10,11 @@
 // A launch's register and LDS allocation is that of its largest tile.  The
 // 6-qubit tiles need 256 VGPRs and about 150 KB of LDS, which leaves room for
 // one 512-thread workgroup per CU (two wavefronts per SIMD); tiles of up to 5
-// qubits fit in 128 VGPRs, i.e. twice the resident wavefronts.  So the 6-qubit tiles form one launch (k_chains_batch<6>, 512-
-// thread workgroups) and all smaller tiles another (k_chains_batch<5>,
-// 256-thread workgroups), back to back on the stream.
+// qubits fit in 128 VGPRs, i.e. twice the resident wavefronts.  So the batch
+// runs as up to three launches per precision back to back on the stream: the
+// 6-qubit tiles (k_chains_batch<6, .>, 512-thread workgroups), the 5-qubit
+// tiles (k_chains_batch<5, .>) and all smaller ones (k_chains_batch<4, .>),
+// the last two with 256-thread workgroups.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,12 +24,13 @@
 
 namespace qst {
 
-// Workgroup size of each launch class: 512 threads for the 6-qubit tiles
-// (one 512-thread team), 256 for tiles of up to 5 qubits, so that a 5-qubit
+// Launch classes: tiles of 1..4 qubits (class 4), 5-qubit tiles (class 5),
+// 6-qubit tiles (class 6).  Workgroup size of each class: 512 threads for
+// the 6-qubit tiles (one 512-thread team), 256 otherwise, so that a 5-qubit
 // tile is one 256-thread team with barriers of its own, as in its
 // single-problem launch.
+constexpr int batch_class(int q) { return q <= 4 ? 4 : q; }
 constexpr int batch_wg(int qmax) { return qmax == 6 ? 512 : 256; }
-constexpr int batch_class(int q) { return q == 6 ? 6 : 5; }
 
 struct BatchItem {
     int32_t problem;   // index into the ChainArgs array
@@ -57,13 +60,10 @@ constexpr size_t batch_lds_doubles()
            WgTables<Q>::kDoubles;
 }
 
-// One tile of qubit count Q.  Each qubit count is a callee of its own, with
-// the dynamic LDS declared here so that its accesses stay LDS instructions:
-// with all six chain steps inlined into one body the kernel needed long
-// branches and heavy register spilling, and its 5-qubit tiles computed wrong
-// likelihoods.
+// One tile of qubit count Q, with the dynamic LDS declared here so that its
+// accesses stay LDS instructions when the tile is a callee of its own.
 template <int Q, int PREC, int QMAX>
-__device__ __attribute__((noinline)) void batch_tile(const ChainArgs& A, int64_t chain0)
+__device__ __forceinline__ void batch_tile_body(const ChainArgs& A, int64_t chain0)
 {
     extern __shared__ double batch_lds[];
     static_assert(batch_class(Q) == QMAX, "a tile runs in the launch of its class");
@@ -74,21 +74,33 @@ __device__ __attribute__((noinline)) void batch_tile(const ChainArgs& A, int64_t
                                                               batch_lds + WgTables<Q>::kDoubles);
 }
 
-// Tiles of QMAX = 5 (qubit counts 1..5) or QMAX = 6 (6 qubits only).  The
-// host sorts every tile into the launch of its class; a tile of the other
-// class is left alone here rather than run with the wrong sizes.
+// In the launch that mixes qubit counts each count is a callee of its own:
+// with several chain steps inlined into one body the kernel needed long
+// branches and heavy register spilling (and, with all six inlined, its
+// 5-qubit tiles computed wrong likelihoods).  The single-count classes inline
+// their one tile, as the single-problem kernel does.
+template <int Q, int PREC, int QMAX>
+__device__ __attribute__((noinline)) void batch_tile(const ChainArgs& A, int64_t chain0)
+{
+    batch_tile_body<Q, PREC, QMAX>(A, chain0);
+}
+
+// The tiles of class QMAX.  The host sorts every tile into the launch of
+// its class; a tile of another class is left alone here rather than run with
+// the wrong sizes.
 template <int PREC, int QMAX>
 __device__ __forceinline__ void batch_dispatch(int q, const ChainArgs& A, int64_t chain0)
 {
     if constexpr (QMAX == 6) {
-        if (q == 6) batch_tile<6, PREC, 6>(A, chain0);
+        if (q == 6) batch_tile_body<6, PREC, 6>(A, chain0);
+    } else if constexpr (QMAX == 5) {
+        if (q == 5) batch_tile_body<5, PREC, 5>(A, chain0);
     } else {
         switch (q) {
-            case 1: batch_tile<1, PREC, 5>(A, chain0); break;
-            case 2: batch_tile<2, PREC, 5>(A, chain0); break;
-            case 3: batch_tile<3, PREC, 5>(A, chain0); break;
-            case 4: batch_tile<4, PREC, 5>(A, chain0); break;
-            case 5: batch_tile<5, PREC, 5>(A, chain0); break;
+            case 1: batch_tile<1, PREC, 4>(A, chain0); break;
+            case 2: batch_tile<2, PREC, 4>(A, chain0); break;
+            case 3: batch_tile<3, PREC, 4>(A, chain0); break;
+            case 4: batch_tile<4, PREC, 4>(A, chain0); break;
             default: break;
         }
     }
@@ -99,20 +111,22 @@ __device__ __forceinline__ void batch_dispatch(int q, const ChainArgs& A, int64_
 template <int QMAX>
 constexpr int batch_waves_per_simd() { return QMAX == 6 ? 2 : 4; }
 
-template <int QMAX>
+// One launch per (class, precision): each holds the tiles of one class in
+// one precision, so a single-count class inlines exactly one chain step.
+template <int QMAX, int PREC>
 __global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void k_chains_batch(BatchArgs B)
 {
     __shared__ int32_t take;
     for (;;) {
         if (threadIdx.x == 0) take = atomicAdd(B.counter, 1);
         __syncthreads();
-        const int32_t it = take;
+        // the same for every thread: the tile's arguments become scalar loads
+        const int32_t it = __builtin_amdgcn_readfirstlane(take);
         __syncthreads();
         if (it >= B.n_items) break;
         const BatchItem I = B.items[it];
         const ChainArgs A = B.problems[I.problem];
-        if (I.prec == kPrecF32) batch_dispatch<kPrecF32, QMAX>(I.q, A, I.chain0);
-        else batch_dispatch<kPrecF64, QMAX>(I.q, A, I.chain0);
+        if (I.prec == PREC) batch_dispatch<PREC, QMAX>(I.q, A, I.chain0);
         __syncthreads();
     }
 }

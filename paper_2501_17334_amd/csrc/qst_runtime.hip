@@ -833,9 +833,10 @@ double chain_step_cost(int Q)
     return c[Q];
 }
 
-// One persistent launch per resource class (6-qubit tiles, then tiles of up
-// to 5 qubits), each over its own largest-first tile list and counter.
-template <int QMAX>
+// One persistent launch per launch class (6-qubit tiles, 5-qubit tiles,
+// tiles of 1..4 qubits) and precision, each over its own largest-first tile
+// list and counter.
+template <int QMAX, int PREC>
 void launch_batch_class(const std::vector<qst::BatchItem>& sorted, size_t lds, const qst::ChainArgs* dargs,
                         qst::BatchItem* ditems, int32_t* counter, hipStream_t s)
 {
@@ -843,18 +844,18 @@ void launch_batch_class(const std::vector<qst::BatchItem>& sorted, size_t lds, c
     if (sorted.size() > 0x7fffffff) fail(QST_ERR_INVALID, "batch too large");
     hip_check(hipMemcpy(ditems, sorted.data(), sizeof(qst::BatchItem) * sorted.size(), hipMemcpyHostToDevice),
               "copy batch tiles");
-    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_batch<QMAX>), lds);
+    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_batch<QMAX, PREC>), lds);
     int dev = 0, n_cu = 0, per_cu = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
     hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
-    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qst::k_chains_batch<QMAX>, qst::batch_wg(QMAX), lds),
+    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qst::k_chains_batch<QMAX, PREC>, qst::batch_wg(QMAX), lds),
               "occupancy");
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(sorted.size()),
                                                                  static_cast<int64_t>(n_cu) * std::max(per_cu, 1)));
     hipLaunchKernelGGL(qst::k_zero_counter, dim3(1), dim3(1), 0, s, counter);
     hip_check(hipGetLastError(), "counter reset");
     qst::BatchArgs b{dargs, ditems, static_cast<int32_t>(sorted.size()), counter};
-    hipLaunchKernelGGL(qst::k_chains_batch<QMAX>, dim3(static_cast<unsigned>(grid)), dim3(qst::batch_wg(QMAX)), lds, s, b);
+    hipLaunchKernelGGL((qst::k_chains_batch<QMAX, PREC>), dim3(static_cast<unsigned>(grid)), dim3(qst::batch_wg(QMAX)), lds, s, b);
     hip_check(hipGetLastError(), "batch kernel launch");
     // the tile list and the counter are reused by the next class
     hip_check(hipStreamSynchronize(s), "batch synchronize");
@@ -865,7 +866,7 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
     std::vector<qst::ChainArgs> args(n);
     std::vector<qst::BatchItem> items;
     std::vector<double> cost;
-    size_t lds_small = 0, lds_big = 0;   // tiles of 1..5 qubits; 6-qubit tiles
+    size_t lds_class[7] = {0, 0, 0, 0, 0, 0, 0};   // by launch class (4, 5, 6)
     for (int i = 0; i < n; ++i) {
         qst_problem* p = problems[i];
         if (p->path != QST_PATH_KRON)
@@ -878,25 +879,33 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
             cost.push_back(chain_step_cost(p->Q) * static_cast<double>(std::min<int64_t>(per, p->R - c0)) *
                            static_cast<double>(std::max<int64_t>(runs[i].n_steps, 1)));
         }
-        size_t& l = p->Q == 6 ? lds_big : lds_small;
+        size_t& l = lds_class[qst::batch_class(p->Q)];
         l = std::max(l, batch_lds_bytes(p->Q));
     }
     std::vector<size_t> order(items.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<qst::BatchItem> small, big;
-    for (size_t i : order) (items[i].q == 6 ? big : small).push_back(items[i]);
+    std::vector<qst::BatchItem> by_class[7][2];   // [class][precision]
+    for (size_t i : order) by_class[qst::batch_class(items[i].q)][items[i].prec].push_back(items[i]);
+    size_t most = 1;
+    for (const auto& c : by_class)
+        for (const auto& v : c) most = std::max(most, v.size());
 
     qst::ChainArgs* dargs = dev_alloc<qst::ChainArgs>(args.size());
     qst::BatchItem* ditems = nullptr;
     int32_t* counter = nullptr;
     try {
-        ditems = dev_alloc<qst::BatchItem>(std::max<size_t>(1, std::max(small.size(), big.size())));
+        ditems = dev_alloc<qst::BatchItem>(most);
         counter = dev_alloc<int32_t>(1);
         hip_check(hipMemcpy(dargs, args.data(), sizeof(qst::ChainArgs) * args.size(), hipMemcpyHostToDevice),
                   "copy batch problems");
-        launch_batch_class<6>(big, lds_big, dargs, ditems, counter, s);
-        launch_batch_class<5>(small, lds_small, dargs, ditems, counter, s);
+        const int F64 = qst::kPrecF64, F32 = qst::kPrecF32;
+        launch_batch_class<6, qst::kPrecF64>(by_class[6][F64], lds_class[6], dargs, ditems, counter, s);
+        launch_batch_class<6, qst::kPrecF32>(by_class[6][F32], lds_class[6], dargs, ditems, counter, s);
+        launch_batch_class<5, qst::kPrecF64>(by_class[5][F64], lds_class[5], dargs, ditems, counter, s);
+        launch_batch_class<5, qst::kPrecF32>(by_class[5][F32], lds_class[5], dargs, ditems, counter, s);
+        launch_batch_class<4, qst::kPrecF64>(by_class[4][F64], lds_class[4], dargs, ditems, counter, s);
+        launch_batch_class<4, qst::kPrecF32>(by_class[4][F32], lds_class[4], dargs, ditems, counter, s);
     } catch (...) {
         dev_free(dargs);
         dev_free(ditems);
