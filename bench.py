@@ -382,7 +382,7 @@ def delayed_acceptance(qst, surrogate, synth, torch, np, name="c4", warm=4000, p
 
 def uneven_batch(qst, synth, torch, np, steps=20):
     """The 256-problem batch of 1..6 qubits (256..4096 chains each) in its
-    work-queue launches (per class of qubit counts), against the same problems launched one after another
+    work-queue launches (one per qubit count), against the same problems launched one after another
     with their tuned shapes; both from step 0, the same streams, FP64.  Also
     per qubit count: the problems of that size batched against solo; and the
     whole batch in the FP32 Kronecker form."""
@@ -415,7 +415,7 @@ def uneven_batch(qst, synth, torch, np, steps=20):
                 "speedup_vs_solo_launches": ms_s / ms_b}
 
     out = {"workload": f"256 problems of 1..6 qubits, 256..4096 chains each, {steps} steps from step 0, "
-                       f"FP64 Kronecker route; batch launches (6-, 5- and 1..4-qubit tiles) vs one launch per problem "
+                       f"FP64 Kronecker route; batch launches (one per qubit count) vs one launch per problem "
                        f"(tuned shapes)"}
     out.update(compare(probs))
     out["per_qubit_count"] = {str(q): compare([p for p in probs if p.n_qubits == q]) for q in range(1, 7)}

@@ -11,10 +11,9 @@
 // 6-qubit tiles need 256 VGPRs and about 150 KB of LDS, which leaves room for
 // one 512-thread workgroup per CU (two wavefronts per SIMD); tiles of up to 5
 // qubits fit in 128 VGPRs, i.e. twice the resident wavefronts.  So the batch
-// runs as up to three launches per precision back to back on the stream: the
-// 6-qubit tiles (k_chains_batch<6, .>, 512-thread workgroups), the 5-qubit
-// tiles (k_chains_batch<5, .>) and all smaller ones (k_chains_batch<4, .>),
-// the last two with 256-thread workgroups.
+// runs as one launch per qubit count and precision present, back to back on
+// the stream, largest qubit count first: k_chains_batch<Q, precision>, with
+// 512-thread workgroups for the 6-qubit tiles and 256 otherwise.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,12 +23,11 @@
 
 namespace qst {
 
-// Launch classes: tiles of 1..4 qubits (class 4), 5-qubit tiles (class 5),
-// 6-qubit tiles (class 6).  Workgroup size of each class: 512 threads for
-// the 6-qubit tiles (one 512-thread team), 256 otherwise, so that a 5-qubit
-// tile is one 256-thread team with barriers of its own, as in its
+// Launch classes: one per qubit count.  Workgroup size of each class: 512
+// threads for the 6-qubit tiles (one 512-thread team), 256 otherwise, so that
+// a 5-qubit tile is one 256-thread team with barriers of its own, as in its
 // single-problem launch.
-constexpr int batch_class(int q) { return q <= 4 ? 4 : q; }
+constexpr int batch_class(int q) { return q; }
 constexpr int batch_wg(int qmax) { return qmax == 6 ? 512 : 256; }
 
 struct BatchItem {
@@ -60,50 +58,20 @@ constexpr size_t batch_lds_doubles()
            WgTables<Q>::kDoubles;
 }
 
-// One tile of qubit count Q, with the dynamic LDS declared here so that its
-// accesses stay LDS instructions when the tile is a callee of its own.
-template <int Q, int PREC, int QMAX>
-__device__ __forceinline__ void batch_tile_body(const ChainArgs& A, int64_t chain0)
+// One tile of qubit count Q, inlined into the launch of its class as the
+// single-problem kernel inlines its chain step.  (One launch for all qubit
+// counts, with each count's tile as a callee of its own, needed long
+// branches and heavy register spilling; with all six inlined into one body
+// its 5-qubit tiles computed wrong likelihoods.)
+template <int Q, int PREC>
+__device__ __forceinline__ void batch_tile(const ChainArgs& A, int64_t chain0)
 {
     extern __shared__ double batch_lds[];
-    static_assert(batch_class(Q) == QMAX, "a tile runs in the launch of its class");
-    constexpr int WG = batch_wg(QMAX);
+    constexpr int WG = batch_wg(Q);
     wg_tables_init<Q>(batch_lds, threadIdx.x, WG);
     __syncthreads();
     chain_tile<Q, BatchTeam<Q>::G, WG, kPathKron, PREC>(A, chain0, batch_lds,
                                                               batch_lds + WgTables<Q>::kDoubles);
-}
-
-// In the launch that mixes qubit counts each count is a callee of its own:
-// with several chain steps inlined into one body the kernel needed long
-// branches and heavy register spilling (and, with all six inlined, its
-// 5-qubit tiles computed wrong likelihoods).  The single-count classes inline
-// their one tile, as the single-problem kernel does.
-template <int Q, int PREC, int QMAX>
-__device__ __attribute__((noinline)) void batch_tile(const ChainArgs& A, int64_t chain0)
-{
-    batch_tile_body<Q, PREC, QMAX>(A, chain0);
-}
-
-// The tiles of class QMAX.  The host sorts every tile into the launch of
-// its class; a tile of another class is left alone here rather than run with
-// the wrong sizes.
-template <int PREC, int QMAX>
-__device__ __forceinline__ void batch_dispatch(int q, const ChainArgs& A, int64_t chain0)
-{
-    if constexpr (QMAX == 6) {
-        if (q == 6) batch_tile_body<6, PREC, 6>(A, chain0);
-    } else if constexpr (QMAX == 5) {
-        if (q == 5) batch_tile_body<5, PREC, 5>(A, chain0);
-    } else {
-        switch (q) {
-            case 1: batch_tile<1, PREC, 4>(A, chain0); break;
-            case 2: batch_tile<2, PREC, 4>(A, chain0); break;
-            case 3: batch_tile<3, PREC, 4>(A, chain0); break;
-            case 4: batch_tile<4, PREC, 4>(A, chain0); break;
-            default: break;
-        }
-    }
 }
 
 // Wavefronts per SIMD the launch is compiled for: 4 (128 VGPRs) for tiles of
@@ -111,8 +79,9 @@ __device__ __forceinline__ void batch_dispatch(int q, const ChainArgs& A, int64_
 template <int QMAX>
 constexpr int batch_waves_per_simd() { return QMAX == 6 ? 2 : 4; }
 
-// One launch per (class, precision): each holds the tiles of one class in
-// one precision, so a single-count class inlines exactly one chain step.
+// One launch per (qubit count, precision), inlining exactly one chain step.
+// The host sorts every tile into the launch of its class; a tile of another
+// class is left alone here rather than run with the wrong sizes.
 template <int QMAX, int PREC>
 __global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void k_chains_batch(BatchArgs B)
 {
@@ -126,7 +95,7 @@ __global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void 
         if (it >= B.n_items) break;
         const BatchItem I = B.items[it];
         const ChainArgs A = B.problems[I.problem];
-        if (I.prec == PREC) batch_dispatch<PREC, QMAX>(I.q, A, I.chain0);
+        if (I.q == QMAX && I.prec == PREC) batch_tile<QMAX, PREC>(A, I.chain0);
         __syncthreads();
     }
 }

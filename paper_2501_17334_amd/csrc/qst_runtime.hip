@@ -833,9 +833,8 @@ double chain_step_cost(int Q)
     return c[Q];
 }
 
-// One persistent launch per launch class (6-qubit tiles, 5-qubit tiles,
-// tiles of 1..4 qubits) and precision, each over its own largest-first tile
-// list and counter.
+// One persistent launch per qubit count and precision, each over its own
+// largest-first tile list and counter.
 template <int QMAX, int PREC>
 void launch_batch_class(const std::vector<qst::BatchItem>& sorted, size_t lds, const qst::ChainArgs* dargs,
                         qst::BatchItem* ditems, int32_t* counter, hipStream_t s)
@@ -866,7 +865,7 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
     std::vector<qst::ChainArgs> args(n);
     std::vector<qst::BatchItem> items;
     std::vector<double> cost;
-    size_t lds_class[7] = {0, 0, 0, 0, 0, 0, 0};   // by launch class (4, 5, 6)
+    size_t lds_class[7] = {0, 0, 0, 0, 0, 0, 0};   // by qubit count
     for (int i = 0; i < n; ++i) {
         qst_problem* p = problems[i];
         if (p->path != QST_PATH_KRON)
@@ -899,13 +898,18 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
         counter = dev_alloc<int32_t>(1);
         hip_check(hipMemcpy(dargs, args.data(), sizeof(qst::ChainArgs) * args.size(), hipMemcpyHostToDevice),
                   "copy batch problems");
-        const int F64 = qst::kPrecF64, F32 = qst::kPrecF32;
-        launch_batch_class<6, qst::kPrecF64>(by_class[6][F64], lds_class[6], dargs, ditems, counter, s);
-        launch_batch_class<6, qst::kPrecF32>(by_class[6][F32], lds_class[6], dargs, ditems, counter, s);
-        launch_batch_class<5, qst::kPrecF64>(by_class[5][F64], lds_class[5], dargs, ditems, counter, s);
-        launch_batch_class<5, qst::kPrecF32>(by_class[5][F32], lds_class[5], dargs, ditems, counter, s);
-        launch_batch_class<4, qst::kPrecF64>(by_class[4][F64], lds_class[4], dargs, ditems, counter, s);
-        launch_batch_class<4, qst::kPrecF32>(by_class[4][F32], lds_class[4], dargs, ditems, counter, s);
+        constexpr int F64 = qst::kPrecF64, F32 = qst::kPrecF32;
+        auto both = [&](auto qc) {
+            constexpr int Q = decltype(qc)::value;
+            launch_batch_class<Q, F64>(by_class[Q][F64], lds_class[Q], dargs, ditems, counter, s);
+            launch_batch_class<Q, F32>(by_class[Q][F32], lds_class[Q], dargs, ditems, counter, s);
+        };
+        both(std::integral_constant<int, 6>{});
+        both(std::integral_constant<int, 5>{});
+        both(std::integral_constant<int, 4>{});
+        both(std::integral_constant<int, 3>{});
+        both(std::integral_constant<int, 2>{});
+        both(std::integral_constant<int, 1>{});
     } catch (...) {
         dev_free(dargs);
         dev_free(ditems);

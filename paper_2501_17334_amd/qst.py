@@ -435,9 +435,8 @@ def list_launch_shapes(n_qubits):
 
 
 def run_batch(problems, configs, stats=True, stream=None, traces=None):
-    """qst_run_chains on several problems at once (the uneven batch:
-    work-queue launches per precision for the 6-qubit, the 5-qubit and the
-    1..4-qubit problems).
+    """qst_run_chains on several problems at once (the uneven batch: one
+    work-queue launch per qubit count and precision).
     traces: optional list (one entry per problem, None or a trace dict as in
     Problem.run)."""
     n = len(problems)

@@ -1,5 +1,5 @@
-"""Uneven batches (persistent work-queue launches per precision: 6-qubit,
-5-qubit and 1..4-qubit tiles), and the launch-shape tuner.
+"""Uneven batches (one persistent work-queue launch per qubit count and
+precision), and the launch-shape tuner.
 
 A batch of problems of 1..6 qubits must give each problem exactly (bit for
 bit) what running it alone gives with the same team size, because every
