@@ -102,4 +102,9 @@ __global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void 
 
 __global__ void k_zero_counter(int32_t* c) { c[0] = 0; }
 
+__global__ void k_zero_counters(int32_t* c, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
+}
+
 }  // namespace qst

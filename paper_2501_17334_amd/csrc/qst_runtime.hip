@@ -833,31 +833,25 @@ double chain_step_cost(int Q)
     return c[Q];
 }
 
-// One persistent launch per qubit count and precision, each over its own
-// largest-first tile list and counter.
+// One persistent launch per qubit count and precision over its part of the
+// tile list (n tiles from `items`, largest first) with its own counter.  The
+// launches of a batch are queued back to back on the stream.
 template <int QMAX, int PREC>
-void launch_batch_class(const std::vector<qst::BatchItem>& sorted, size_t lds, const qst::ChainArgs* dargs,
-                        qst::BatchItem* ditems, int32_t* counter, hipStream_t s)
+void launch_batch_class(const qst::BatchItem* items, size_t n, size_t lds, const qst::ChainArgs* dargs,
+                        int32_t* counter, int n_cu, hipStream_t s)
 {
-    if (sorted.empty()) return;
-    if (sorted.size() > 0x7fffffff) fail(QST_ERR_INVALID, "batch too large");
-    hip_check(hipMemcpy(ditems, sorted.data(), sizeof(qst::BatchItem) * sorted.size(), hipMemcpyHostToDevice),
-              "copy batch tiles");
+    if (n == 0) return;
     allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_batch<QMAX, PREC>), lds);
-    int dev = 0, n_cu = 0, per_cu = 0;
-    hip_check(hipGetDevice(&dev), "hipGetDevice");
-    hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
-    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qst::k_chains_batch<QMAX, PREC>, qst::batch_wg(QMAX), lds),
+    int per_cu = 0;
+    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qst::k_chains_batch<QMAX, PREC>,
+                                                           qst::batch_wg(QMAX), lds),
               "occupancy");
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(sorted.size()),
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(n),
                                                                  static_cast<int64_t>(n_cu) * std::max(per_cu, 1)));
-    hipLaunchKernelGGL(qst::k_zero_counter, dim3(1), dim3(1), 0, s, counter);
-    hip_check(hipGetLastError(), "counter reset");
-    qst::BatchArgs b{dargs, ditems, static_cast<int32_t>(sorted.size()), counter};
-    hipLaunchKernelGGL((qst::k_chains_batch<QMAX, PREC>), dim3(static_cast<unsigned>(grid)), dim3(qst::batch_wg(QMAX)), lds, s, b);
+    qst::BatchArgs b{dargs, items, static_cast<int32_t>(n), counter};
+    hipLaunchKernelGGL((qst::k_chains_batch<QMAX, PREC>), dim3(static_cast<unsigned>(grid)),
+                       dim3(qst::batch_wg(QMAX)), lds, s, b);
     hip_check(hipGetLastError(), "batch kernel launch");
-    // the tile list and the counter are reused by the next class
-    hip_check(hipStreamSynchronize(s), "batch synchronize");
 }
 
 void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* runs, hipStream_t s)
@@ -884,25 +878,45 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
     std::vector<size_t> order(items.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<qst::BatchItem> by_class[7][2];   // [class][precision]
-    for (size_t i : order) by_class[qst::batch_class(items[i].q)][items[i].prec].push_back(items[i]);
-    size_t most = 1;
-    for (const auto& c : by_class)
-        for (const auto& v : c) most = std::max(most, v.size());
+    // one list: the classes in launch order (6 qubits first, FP64 before
+    // FP32), each largest first
+    constexpr int kClasses = 12;
+    auto slot = [](int q, int prec) { return 2 * (6 - q) + prec; };
+    std::vector<qst::BatchItem> by_slot[kClasses];
+    for (size_t i : order) by_slot[slot(items[i].q, items[i].prec)].push_back(items[i]);
+    std::vector<qst::BatchItem> all;
+    size_t off[kClasses + 1] = {};
+    for (int k = 0; k < kClasses; ++k) {
+        off[k] = all.size();
+        all.insert(all.end(), by_slot[k].begin(), by_slot[k].end());
+    }
+    off[kClasses] = all.size();
+    for (int k = 0; k < kClasses; ++k)
+        if (off[k + 1] - off[k] > 0x7fffffff) fail(QST_ERR_INVALID, "batch too large");
 
     qst::ChainArgs* dargs = dev_alloc<qst::ChainArgs>(args.size());
     qst::BatchItem* ditems = nullptr;
-    int32_t* counter = nullptr;
+    int32_t* counters = nullptr;
     try {
-        ditems = dev_alloc<qst::BatchItem>(most);
-        counter = dev_alloc<int32_t>(1);
+        ditems = dev_alloc<qst::BatchItem>(std::max<size_t>(1, all.size()));
+        counters = dev_alloc<int32_t>(kClasses);
         hip_check(hipMemcpy(dargs, args.data(), sizeof(qst::ChainArgs) * args.size(), hipMemcpyHostToDevice),
                   "copy batch problems");
+        hip_check(hipMemcpy(ditems, all.data(), sizeof(qst::BatchItem) * all.size(), hipMemcpyHostToDevice),
+                  "copy batch tiles");
+        int dev = 0, n_cu = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+        hipLaunchKernelGGL(qst::k_zero_counters, dim3(1), dim3(64), 0, s, counters, kClasses);
+        hip_check(hipGetLastError(), "counter reset");
         constexpr int F64 = qst::kPrecF64, F32 = qst::kPrecF32;
         auto both = [&](auto qc) {
             constexpr int Q = decltype(qc)::value;
-            launch_batch_class<Q, F64>(by_class[Q][F64], lds_class[Q], dargs, ditems, counter, s);
-            launch_batch_class<Q, F32>(by_class[Q][F32], lds_class[Q], dargs, ditems, counter, s);
+            const int k64 = slot(Q, F64), k32 = slot(Q, F32);
+            launch_batch_class<Q, F64>(ditems + off[k64], off[k64 + 1] - off[k64], lds_class[Q], dargs,
+                                       counters + k64, n_cu, s);
+            launch_batch_class<Q, F32>(ditems + off[k32], off[k32 + 1] - off[k32], lds_class[Q], dargs,
+                                       counters + k32, n_cu, s);
         };
         both(std::integral_constant<int, 6>{});
         both(std::integral_constant<int, 5>{});
@@ -910,15 +924,17 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
         both(std::integral_constant<int, 3>{});
         both(std::integral_constant<int, 2>{});
         both(std::integral_constant<int, 1>{});
+        hip_check(hipStreamSynchronize(s), "batch synchronize");
     } catch (...) {
+        (void)hipStreamSynchronize(s);   // no launch may still read the buffers freed below
         dev_free(dargs);
         dev_free(ditems);
-        dev_free(counter);
+        dev_free(counters);
         throw;
     }
     dev_free(dargs);
     dev_free(ditems);
-    dev_free(counter);
+    dev_free(counters);
 }
 
 }  // namespace
