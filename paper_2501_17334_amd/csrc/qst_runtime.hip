@@ -1160,9 +1160,11 @@ qst_status qst_acf(const double* records, int64_t n_chains, int64_t n_samples, i
         double* outd = nullptr;
         try {
             outd = dev_alloc<double>(l_max + 1);
-            const dim3 grid((l_max + 1 + qst::kAcfLags - 1) / qst::kAcfLags, static_cast<unsigned>(n_chains));
-            hipLaunchKernelGGL(qst::k_acf_partial, grid, dim3(qst::kAcfThreads), 0, s, records, n_samples, D, l_max,
-                               part);
+            const int n_groups = (l_max + 1 + qst::kAcfLags - 1) / qst::kAcfLags;
+            const int64_t blocks = n_chains * n_groups;
+            if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many chains x lags");
+            hipLaunchKernelGGL(qst::k_acf_partial, dim3(static_cast<unsigned>(blocks)), dim3(qst::kAcfThreads), 0, s,
+                               records, n_samples, D, l_max, n_groups, n_chains, part);
             hip_check(hipGetLastError(), "acf launch");
             hipLaunchKernelGGL(qst::k_acf_final, dim3(1), dim3(qst::kAcfThreads), 0, s, part, n_chains, l_max, outd);
             hip_check(hipGetLastError(), "acf final launch");
