@@ -83,13 +83,16 @@ __device__ __forceinline__ double uniform_open(uint64_t w)
 
 // Box-Muller (1958) on one pair of words: r = sqrt(-2 ln u_a),
 // theta = 2 pi u_b -> (r cos theta, r sin theta); ln from the table-driven
-// logarithm, sin/cos(2 pi u_b) as sin/cos(pi x) with x = 2 u_b in (0, 2).
+// logarithm, the root by sqrt_pos, sin/cos(2 pi u_b) as sin/cos(pi x) with
+// x = 2 u_b in (0, 2).  -2 ln u_a lies in [2^-52, 74]; it is clamped at its
+// true minimum 2^-52 because the table logarithm of the largest uniform,
+// 1 - 2^-53, may round to zero or just above, which would make the root NaN.
 __device__ __forceinline__ void box_muller(uint64_t wa, uint64_t wb, double& n0, double& n1,
                                            const LogEntry* __restrict__ logtab)
 {
     const double ua = uniform_open(wa);
     const double ub = uniform_open(wb);
-    const double r = sqrt(-2.0 * fast_log(ua, logtab));
+    const double r = sqrt_pos(fmax(-2.0 * fast_log(ua, logtab), 0x1p-52));
     double s, c;
     sincospi_0_2(2.0 * ub, s, c);
     n0 = r * c;
