@@ -1480,9 +1480,9 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
 
     // ---- Algorithm 2 ----
     int kr = 0;   // position of the step in its group of kRing steps
+    double a = sqrt(1.0 - beta * beta);   // the pCN contraction, recomputed when beta changes
     for (int64_t t = 0; t < A.n_steps; ++t) {
         const int64_t j = A.step_begin + 1 + t;
-        const double a = sqrt(1.0 - beta * beta);
         draw(static_cast<uint64_t>(j), kr);
         kr = kr + 1 == S::kRing ? 0 : kr + 1;
         sync();
@@ -1528,6 +1528,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
                 const double rate = static_cast<double>(acc_w) / static_cast<double>(A.adapt_every);
                 if (rate > A.adapt_hi) beta = fmin(beta * A.adapt_factor, 1.0);
                 if (rate < A.adapt_lo) beta = beta / A.adapt_factor;
+                a = sqrt(1.0 - beta * beta);
             }
             acc_w = 0;
         }
