@@ -10,7 +10,8 @@
  *                        likelihood Eq. (likelihood));
  *   qst_run_chains    -- Step 5: R independent, non-communicating chains of
  *                        Algorithm 2 (pCN with step-size adaptation and
- *                        thinning), all steps in one persistent launch;
+ *                        thinning), all steps in one persistent launch
+ *                        (a batch: one per qubit count and precision);
  *   qst_pool_moments  -- Step 6 / Eq. (BME2) with phi(rho) = rho (and the
  *                        element-wise second moments).
  * Supporting calls: qst_loglik evaluates Eq. (likelihood) for a batch of
