@@ -4,8 +4,10 @@
   stage 2 is the plain Metropolis-Hastings test: the run must equal plain
   pCN bit for bit (same streams, same team shape).
 * Against the oracle's delayed-acceptance rule (FP64 surrogate from the same
-  BF16-rounded weights): identical decisions except where the stage-1 margin
-  |log u1 - ds| is within the GPU/CPU surrogate difference.
+  BF16-rounded weights): the GPU surrogate stays within the a-priori error
+  bound of its arithmetic (tests/mlp_bound.py) on random states, and
+  decisions are identical except where a stage margin lies within that
+  bound at the two states involved.
 * Both stages keep the posterior exact: the pooled mean of a delayed-
   acceptance run agrees with plain pCN within the Monte Carlo error.
 """
@@ -17,6 +19,7 @@ from oracle import mlp_ref as M
 from oracle import oracle as O
 from paper_2501_17334_amd import qst, synth
 from tests.gpu_util import gpu_run
+from tests.mlp_bound import surrogate_error_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -116,15 +119,18 @@ def test_matches_oracle_delayed_acceptance():
     ch = O.Chains(Q, prob.counts, O.RunParams(n_chains=R, n_steps=0, seed=prob.seed, beta0=beta, adapt_every=0,
                                               trace_chains=R, surrogate=w))
     o = ch.run(T)
-    # the GPU surrogate (BF16 weights and activations, FP32 sums) against the
-    # oracle's FP64 one: the guard band for decisions
+    # the GPU surrogate (BF16 inputs, weights and activations, FP32 sums)
+    # against the oracle's FP64 one, within the a-priori bound of its arithmetic
+    bound = lambda X: surrogate_error_bound(w.W1, w.b1, w.W2, w.b2, w.w3, w.b3, scale, shift, X)
     xs = np.random.default_rng(8).standard_normal((512, d))
     xpad = np.zeros((512, dp))
     xpad[:, :d] = xs
     s_gpu = net.predict(torch.from_numpy(xpad).cuda()).cpu().numpy().astype(np.float64)
     s_cpu = np.array([O.mlp_forward(w, x) for x in xs])
-    band = 4.0 * np.max(np.abs(s_gpu - s_cpu)) + 1e-6
-    print(f"[da oracle] surrogate GPU-CPU max diff {np.max(np.abs(s_gpu - s_cpu)):.3e}", flush=True)
+    gap, bnd = np.abs(s_gpu - s_cpu), bound(xs)
+    print(f"[da oracle] surrogate GPU-CPU max diff {gap.max():.3e}, a-priori bound max {bnd.max():.3e}",
+          flush=True)
+    assert np.all(gap <= bnd), np.max(gap / bnd)
     agree = 0
     a_beta = np.sqrt(1.0 - beta * beta)
     for r in range(R):
@@ -146,6 +152,7 @@ def test_matches_oracle_delayed_acceptance():
             j = k + 1
             yp = a_beta * y + beta * O.normals(prob.seed, r, j, d)
             ds = O.mlp_forward(w, yp) - O.mlp_forward(w, y)
+            band = float(np.sum(bound(np.stack([yp, y]))))   # |ds_gpu - ds_cpu| at most
             m1 = abs(np.log(O.da_uniform(prob.seed, r, j)) - ds)
             if ev_g[k] != ev_o[k]:
                 assert m1 <= band, (r, k, m1, band)
