@@ -26,8 +26,21 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (published)
 
 
+def algorithmic_flops_per_chain_step(Q):
+    """The algorithmic work of one chain-step that the roofline prices: the
+    Kronecker-factored contraction (Q per-qubit 4 -> 6 maps on the Hermitian
+    tensor, sum_q 8 6^q 4^(Q-q) flop: 24,960 at 4 qubits) plus the rho build
+    (a Hermitian rank-D complex update, 4 D^3 flop: 16,384 at 4 qubits);
+    41,344 flop at 4 qubits.  Normals and logarithms are counts, not flops."""
+    D = 2 ** Q
+    contraction = sum(8 * 6 ** q * 4 ** (Q - q) for q in range(1, Q + 1))
+    return contraction + 4 * D ** 3
+
+
 def flops_per_chain_step(Q, stored_fraction):
-    """Algorithmic FP64 flops of one chain-step (roofline)."""
+    """Every FP64 flop of the method's arithmetic in one chain-step (proposal,
+    weights, rho, contraction, count-weighted log sum, moments): reported
+    beside the roofline, which prices the algorithmic work only."""
     D = 2 ** Q
     d = 2 * D * D + D
     KD = 6 ** Q
@@ -380,12 +393,13 @@ def delayed_acceptance(qst, surrogate, synth, torch, np, name="c4", warm=4000, p
     }
 
 
-def uneven_batch(qst, synth, torch, np, steps=20):
+def uneven_batch(qst, synth, torch, np, steps=200, full_steps=2000):
     """The 256-problem batch of 1..6 qubits (256..4096 chains each) in its
-    work-queue launches (one per qubit count), against the same problems launched one after another
-    with their tuned shapes; both from step 0, the same streams, FP64.  Also
-    per qubit count: the problems of that size batched against solo; and the
-    whole batch in the FP32 Kronecker form."""
+    work-queue launches, against the same problems launched one after
+    another with their tuned shapes; both from step 0, the same streams,
+    FP64, `steps` steps.  Also per qubit count: the problems of that size
+    batched against solo; the whole batch in the FP32 Kronecker form; and the
+    batch over the workload's full 2000 steps in both precisions."""
     probs = synth.mixed_batch(256)
 
     def timed(fn):
@@ -415,8 +429,8 @@ def uneven_batch(qst, synth, torch, np, steps=20):
                 "speedup_vs_solo_launches": ms_s / ms_b}
 
     out = {"workload": f"256 problems of 1..6 qubits, 256..4096 chains each, {steps} steps from step 0, "
-                       f"FP64 Kronecker route; batch launches (one per qubit count) vs one launch per problem "
-                       f"(tuned shapes)"}
+                       f"FP64 Kronecker route; the batch call vs one launch per problem (tuned shapes); "
+                       f"and the batch over {full_steps} steps (M_A = 500)"}
     out.update(compare(probs))
     out["per_qubit_count"] = {str(q): compare([p for p in probs if p.n_qubits == q]) for q in range(1, 7)}
     # forms (1) and (2) together: the same batch with every problem in the FP32 Kronecker form
@@ -424,6 +438,20 @@ def uneven_batch(qst, synth, torch, np, steps=20):
     out["fp32_form"] = {k: f32[k] for k in ("batch_ms", "solo_ms", "batch_chain_steps_per_s",
                                             "solo_chain_steps_per_s", "speedup_vs_solo_launches")}
     out["fp32_form"]["batch_speedup_vs_fp64_batch"] = out["batch_ms"] / f32["batch_ms"]
+    full = {}
+    for precision in ("fp64", "fp32"):
+        cfgs = [qst.RunConfig(n_chains=p.n_chains, n_steps=full_steps, seed=p.seed, beta0=0.05, adapt_every=500)
+                for p in probs]
+        handles = [qst.Problem(p.n_qubits, p.counts, precision=precision, path="kron") for p in probs]
+        qst.run_batch(handles, [qst.RunConfig(n_chains=c.n_chains, n_steps=2, seed=c.seed) for c in cfgs],
+                      stats=False)
+        work = sum(c.n_chains for c in cfgs) * full_steps
+        ms = timed(lambda: qst.run_batch(handles, cfgs, stats=False))
+        full[precision] = {"ms": ms, "chain_steps": work, "chain_steps_per_s": work / (ms / 1e3)}
+        for h in handles:
+            h.close()
+    full["fp32_speedup"] = full["fp64"]["ms"] / full["fp32"]["ms"]
+    out[f"full_{full_steps}_steps"] = full
     return out
 
 
@@ -437,24 +465,89 @@ def pilot_beta(qst, P, seed, n_chains=256, n_steps=6000):
     return float(np.median(beta)), st
 
 
-def cpu_baseline(prob, target_s):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, target_s, ess_per_chain_step=None, parity_runs=True):
     """The FP64 oracle on this host's cores, on a bounded sample of the same
-    workload: 16 x threads chains from step 0, steps sized for ~target_s."""
+    workload: 16 x threads chains from step 0, steps sized for ~target_s;
+    then the same on one thread (a shorter sample), and the full 1- and
+    2-qubit parity runs (64 x 2000 and 4096 x 10^4 chain-steps).  The
+    oracle's ESS/s is its rate times the ESS per chain-step of the GPU run
+    of the same algorithm (the chains are the same up to rounding)."""
     from oracle import oracle as O
+    from paper_2501_17334_amd import synth
     threads = O.num_threads()
+
+    def rate_on(p, R, seconds, beta0, adapt_every=500):
+        ch = O.Chains(p.n_qubits, p.counts, O.RunParams(n_chains=R, n_steps=0, seed=p.seed, beta0=beta0,
+                                                       adapt_every=adapt_every))
+        t0 = time.perf_counter()
+        ch.run(2)
+        rate = 2 * R / (time.perf_counter() - t0)
+        steps = max(4, int(seconds * rate / R))
+        t0 = time.perf_counter()
+        ch.run(steps)
+        dt = time.perf_counter() - t0
+        return R * steps / dt, steps, dt
+
     R = 16 * threads
-    ch = O.Chains(prob.n_qubits, prob.counts, O.RunParams(n_chains=R, n_steps=0, seed=prob.seed,
-                                                          beta0=0.01, adapt_every=500))
-    t0 = time.perf_counter()
-    ch.run(2)
-    rate = 2 * R / (time.perf_counter() - t0)
-    steps = max(4, int(target_s * rate / R))
-    t0 = time.perf_counter()
-    ch.run(steps)
-    dt = time.perf_counter() - t0
-    return {"value": R * steps / dt, "unit": "chain-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{R} chains x {steps} pCN steps of the 4-qubit workload (steps 3..{steps + 2}), "
-                      f"{dt:.1f} s of FP64 CPU work"}
+    value, steps, dt = rate_on(prob, R, target_s, 0.01)
+    O.set_num_threads(1)
+    try:
+        one, steps1, dt1 = rate_on(prob, 4, target_s / 4, 0.01)
+    finally:
+        O.set_num_threads(threads)
+    out = {"value": value, "unit": "chain-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{R} chains x {steps} pCN steps of the {prob.n_qubits}-qubit workload (steps 3..{steps + 2}), "
+                     f"{dt:.1f} s of FP64 CPU work on {threads} threads",
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "one_core": {"value": one, "unit": "chain-steps/s",
+                        "sample": f"4 chains x {steps1} steps on one thread, {dt1:.1f} s"}}
+    if ess_per_chain_step:
+        out["ess_per_s"] = value * ess_per_chain_step
+        out["ess_per_s_note"] = "oracle chain-steps/s x the GPU run's ESS per chain-step (same algorithm)"
+    if parity_runs:
+        runs = {}
+        for name in ("c1", "c2"):
+            p = synth.make_problem(name)
+            ch = O.Chains(p.n_qubits, p.counts, O.RunParams(n_chains=p.n_chains, n_steps=0, seed=p.seed,
+                                                           beta0=p.extra.get("beta0", 0.05), adapt_every=500))
+            t0 = time.perf_counter()
+            ch.run(p.n_steps)
+            dt = time.perf_counter() - t0
+            runs[name] = {"chains": p.n_chains, "steps": p.n_steps, "seconds": dt,
+                          "chain_steps_per_s": p.n_chains * p.n_steps / dt}
+        out["parity_runs_full"] = runs
+    return out
+
+
+def calibrate_copy(torch, mib, reps=3):
+    """A plain device-to-device copy of a known size: run under
+    `rocprofv3 --pmc FETCH_SIZE` (then `WRITE_SIZE`), each copy dispatch reads
+    and writes mib MiB, and the ratio of a counter to that figure scales the
+    same counter of another kernel on the same machine."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for r in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        print(f"copy {r}: {n * 8} bytes read + {n * 8} written in {ms:.3f} ms ({2 * n * 8 / ms / 1e6:.1f} GB/s)",
+              flush=True)
 
 
 def main():
@@ -466,6 +559,10 @@ def main():
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--nsteps", type=int, default=10000)
     ap.add_argument("--burn-in", type=int, default=5000)
+    ap.add_argument("--record-every", type=int, default=4)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (the known-size "
+                         "dispatch that scales rocprofv3's FETCH_SIZE/WRITE_SIZE counters) and exit")
     ap.add_argument("--path", default="auto")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -483,6 +580,10 @@ def main():
     import numpy as np
     import torch
 
+    if args.calibrate_copy:
+        calibrate_copy(torch, args.calibrate_copy)
+        return
+
     from paper_2501_17334_amd import qst, synth
 
     dev = torch.device("cuda:0")
@@ -497,7 +598,9 @@ def main():
     print(f"[bench] pilot beta={beta:.5g} (acceptance {pst['accepted'] / pst['proposed']:.3f})",
           file=sys.stderr, flush=True)
 
-    rec_every, rec_chains = 8, min(256, R)
+    # 1250 recorded samples per chain after the burn-in (every 4 steps of the
+    # last 5000): Eq. (IACT) needs N well above tau for a trustworthy sum
+    rec_every, rec_chains = args.record_every, min(256, R)
     rec = torch.zeros((rec_chains, NT // rec_every, D, D), dtype=torch.float64, device=dev)
     cfg = qst.RunConfig(n_chains=R, n_steps=NT, seed=prob.seed, beta0=beta, thin=1, burn_in=burn,
                         adapt_every=500)
@@ -534,20 +637,32 @@ def main():
     chain_steps = R * NT
     value = chain_steps / (ms_step / 1e3)
 
-    # pooled ESS: Eq. (IACT) on the recorded chains after burn-in (spacing 8 steps)
+    # pooled ESS two ways: N_eff = N R / tau with tau from Eq. (IACT) on the
+    # recorded chains after the burn-in, and the between-chain ESS
+    # tr Var_post / SE^2 of the independent chains
     first = (burn + rec_every - 1) // rec_every
     n_rec = NT // rec_every - first
     l_max = min(200, n_rec - 1)
     c = qst.acf(rec[:, first:].contiguous(), l_max=l_max)
     tau = qst.iact(c)
-    n_eff = n_rec * R / tau
+    n_eff_iact = n_rec * R / tau
     var = np.concatenate([(pool["second_re"] - pool["mean"].real ** 2).ravel(),
                           (pool["second_im"] - pool["mean"].imag ** 2).ravel()])
     se2 = np.concatenate([pool["se_re"].ravel() ** 2, pool["se_im"].ravel() ** 2])
     ess_between = float(np.sum(var) / np.sum(se2))
+    # Eq. (IACT) truncated at l_max is only trustworthy when the ACF has died
+    # out there: flag a tail still above 0.05, a sum pulled down by negative
+    # values (each chain is centred on its own mean, which biases every c[l]
+    # low by about tau/N), and disagreement with the between-chain ESS; the
+    # headline ESS is the smaller of the two estimates
+    ratio = n_eff_iact / ess_between
+    ess_flags = {"tail_above_0.05": bool(c[-1] > 0.05), "acf_below_-0.05": bool(np.min(c) < -0.05),
+                 "iact_vs_between_ratio_beyond_1.5": bool(ratio > 1.5 or ratio < 1 / 1.5)}
+    n_eff = min(n_eff_iact, ess_between)
 
     stored_fraction = (NT - burn) / NT
-    flop = flops_per_chain_step(Q, stored_fraction)
+    flop_all = flops_per_chain_step(Q, stored_fraction)
+    flop = algorithmic_flops_per_chain_step(Q)
     achieved = flop * chain_steps / (ms_kernel / 1e3) / 1e12
     khash = kernel_source_hash()
     traffic = measured_traffic(khash, f"chain_kernel_q{Q}_{args.config}")
@@ -574,17 +689,24 @@ def main():
             "beta0_from_pilot": beta,
         },
         "ess_per_s": n_eff / (ms_step / 1e3),
-        "ess": {"n_eff": n_eff, "tau": tau, "tau_spacing_steps": rec_every, "l_max": l_max,
-                "c_lmax": float(c[-1]), "upper_bound": bool(c[-1] > 0.05),
-                "between_chain_ess": ess_between,
-                "between_chain_ess_per_s": ess_between / (ms_step / 1e3)},
+        "ess": {"headline": "min(IACT ESS, between-chain ESS)", "n_eff": n_eff,
+                "iact_n_eff": n_eff_iact, "iact_ess_per_s": n_eff_iact / (ms_step / 1e3),
+                "tau": tau, "tau_steps": tau * rec_every, "tau_spacing_steps": rec_every,
+                "records_per_chain": n_rec, "recorded_chains": rec_chains, "l_max": l_max,
+                "c_lmax": float(c[-1]), "c_min": float(np.min(c)),
+                "iact_upper_bound": bool(any(ess_flags.values())), "flags": ess_flags,
+                "between_chain_ess": ess_between, "between_chain_ess_per_s": ess_between / (ms_step / 1e3),
+                "iact_over_between": ratio},
         "acceptance_note": "adaptation per Algorithm 2 (M_A=500) from the pilot beta",
         "mean_error_to_truth_frobenius": float(np.sqrt(np.sum(np.abs(pool["mean"] - prob.truth.density_matrix())
                                                                ** 2))),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": f"k_chains<Q={Q}>", "kernel_ms": ms_kernel,
-                     "flop_per_chain_step": flop, "kernel_source_hash": khash},
+                     "flop_per_chain_step": flop, "chain_steps_per_launch": chain_steps,
+                     "all_arith_flop_per_chain_step": flop_all,
+                     "all_arith_frac": flop_all * chain_steps / (ms_kernel / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
+                     "kernel_source_hash": khash},
     }
     if not args.no_forms:
         print("[bench] chosen forms", file=sys.stderr, flush=True)
@@ -604,7 +726,7 @@ def main():
         out["dense_gemm"] = dense_gemm_rates(qst, synth, torch, prob)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, ess_per_chain_step=n_eff / chain_steps)
     print(json.dumps(out), flush=True)
 
 

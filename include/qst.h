@@ -38,8 +38,9 @@
  * A uniform is ((w >> 12) + 1/2) 2^-52; normal i of a step comes from block
  * i/4 by Box-Muller on the word pairs (0,1) and (2,3).  Step 0 draws the
  * initial state; step j >= 1 the proposal of step j.  A chain's numbers are
- * a function of (seed, chain index within its problem, step) only, so any
- * subset, batch or resumed run reproduces the same chains.
+ * a function of (seed, chain index within its problem, step) only, so a
+ * batched or resumed run reproduces the same chains, and so does a run of
+ * any contiguous range of chain indices (qst_run_desc.chain_offset).
  *
  * Errors: every call returns a qst_status; no C++ exception crosses this
  * boundary.  On failure, outputs are unspecified and qst_last_error() gives
@@ -196,6 +197,12 @@ typedef struct {
     uint16_t* pair_x;
     double* pair_ll;
     void* stream;            /* hipStream_t the work is queued on (NULL = default stream) */
+    /* index of the handle's first chain within its problem (>= 0): local
+     * chain r draws the random numbers of chain chain_offset + r, so a range
+     * of chains run alone (for instance one that failed) equals the same
+     * range of a larger run.  Fixed after the first run of a handle unless
+     * resume = 0 (QST_ERR_INVALID otherwise). */
+    int64_t chain_offset;
 } qst_run_desc;
 
 typedef struct {
@@ -308,10 +315,12 @@ qst_status qst_mlp_predict(qst_mlp* h, const uint16_t* x, int64_t n, float* out,
  * QST_ERR_INVALID if a value is not finite or all are equal. */
 qst_status qst_mlp_targets(const double* ll, int64_t n, float* y, double* mean, double* sd, void* stream);
 /* rows of a training set in a given order: xo[k] = x[idx[k]] (width BF16
- * values per row), yo[k] = y[idx[k]]; all DEVICE; idx entries must be valid
- * row indices of x and y (not checked). */
-qst_status qst_gather_rows(const uint16_t* x, int32_t width, const float* y, const int64_t* idx, int64_t n,
-                           uint16_t* xo, float* yo, void* stream);
+ * values per row), yo[k] = y[idx[k]]; all DEVICE; x holds n_rows rows and y
+ * n_rows values.  Every idx entry is checked to lie in [0, n_rows) before the
+ * gather is queued (QST_ERR_INVALID otherwise; the check copies idx to the
+ * host and waits for `stream`). */
+qst_status qst_gather_rows(const uint16_t* x, int32_t width, const float* y, int64_t n_rows, const int64_t* idx,
+                           int64_t n, uint16_t* xo, float* yo, void* stream);
 /* the frozen surrogate for qst_run_desc.surrogate (pointers into h; valid while h lives) */
 qst_status qst_mlp_surrogate(const qst_mlp* h, qst_surrogate* out);
 

@@ -89,6 +89,7 @@ def lib():
         L.orc_eval_batch.argtypes = [C.c_int, c_int64_p, C.c_int64, c_double_p, c_double_p,
                                      c_double_p]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_pool.argtypes = [C.c_int, C.c_int64, c_double_p, c_double_p, c_int64_p,
                                c_double_p, c_double_p]
         _lib = L
@@ -102,6 +103,11 @@ def _p(a, t=c_double_p):
 def num_threads():
     """OpenMP threads the oracle's parallel loops use."""
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's later parallel loops."""
+    lib().orc_set_num_threads(int(n))
 
 
 # parameterisations: the Gaussian/gamma form (2D^2+D parameters) and the

@@ -760,3 +760,10 @@ int orc_num_threads(void)
     }
     return n;
 }
+
+/* Set the number of threads of the oracle's parallel loops (the baseline
+ * timing uses one thread for its single-core figure). */
+void orc_set_num_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}

@@ -58,7 +58,8 @@ struct ChainArgs {
     const double* ndv;      // [KD] counts, task-major order of the likelihood transforms (LikSplit)
     const uint16_t* muv;    // [KD] Pauli indices in the same order
     const void* mfrag;      // dense path: the Pauli matrix in MFMA fragment order
-    int64_t R;              // chains of the problem
+    int64_t R;              // chains of this handle
+    int64_t chain0;         // problem-wide index of chain 0 (its Philox counter word)
     double* x;              // [R][d] current state
     double* ll;             // [R] log L of the current state
     double* beta;           // [R]
@@ -1319,7 +1320,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         const bool normal = job < NB;
         const uint64_t c0 = normal ? static_cast<uint64_t>(job) : 0;
         const uint64_t c3 = normal ? 0 : (static_cast<uint64_t>(kTagMH) << 56);
-        const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(c), c3, A.seed, 0);
+        const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(A.chain0 + c), c3, A.seed, 0);
         if (normal) {
             box_muller(B.w[0], B.w[1], v[0], v[1], logtab);
             box_muller(B.w[2], B.w[3], v[2], v[3], logtab);

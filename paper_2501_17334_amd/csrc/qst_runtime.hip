@@ -455,6 +455,7 @@ struct qst_problem {
     }
     // chain state
     int64_t R = 0;
+    int64_t chain0 = 0;     // index of chain 0 of this handle within its problem (qst_run_desc.chain_offset)
     int64_t step = 0;
     bool have_run = false;
     double *x = nullptr, *ll = nullptr, *beta = nullptr, *rho = nullptr, *s1 = nullptr, *s2 = nullptr;
@@ -570,9 +571,11 @@ void validate_run(const qst_problem* p, const qst_run_desc& r)
         check_device_buffer(r.pair_x, rows * p->da_width() * sizeof(uint16_t), p->device, "pair_x");
         check_device_buffer(r.pair_ll, rows * sizeof(double), p->device, "pair_ll");
     }
+    if (r.chain_offset < 0) fail(QST_ERR_INVALID, "chain_offset must be >= 0");
     if (r.resume) {
         if (!p->have_run) fail(QST_ERR_STATE, "resume requested before any run of this handle");
         if (r.n_chains != p->R) fail(QST_ERR_INVALID, "resume with a different n_chains");
+        if (r.chain_offset != p->chain0) fail(QST_ERR_INVALID, "resume with a different chain_offset");
     }
     if (r.surrogate) {
         if (!r.surrogate->model) fail(QST_ERR_INVALID, "surrogate has no model (use qst_mlp_surrogate)");
@@ -726,6 +729,7 @@ void prepare_state(qst_problem* p, const qst_run_desc& r)
             p->alloc_state(r.n_chains);
         }
         p->step = 0;
+        p->chain0 = r.chain_offset;
     }
 }
 
@@ -738,6 +742,7 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
     a.muv = p->muv;
     a.mfrag = p->path == QST_PATH_DENSE ? p->fragments(p->precision) : nullptr;
     a.R = p->R;
+    a.chain0 = p->chain0;
     a.x = p->x;
     a.ll = p->ll;
     a.beta = p->beta;
@@ -1514,23 +1519,33 @@ qst_status qst_mlp_targets(const double* ll, int64_t n, float* y, double* mean, 
     });
 }
 
-qst_status qst_gather_rows(const uint16_t* x, int32_t width, const float* y, const int64_t* idx, int64_t n,
-                           uint16_t* xo, float* yo, void* stream)
+qst_status qst_gather_rows(const uint16_t* x, int32_t width, const float* y, int64_t n_rows, const int64_t* idx,
+                           int64_t n, uint16_t* xo, float* yo, void* stream)
 {
     return guarded([&] {
         if (!x || !y || !idx || !xo || !yo) fail(QST_ERR_INVALID, "NULL argument");
-        if (n < 0 || width < 1) fail(QST_ERR_INVALID, "bad sizes");
+        if (n < 0 || width < 1 || n_rows < 1) fail(QST_ERR_INVALID, "bad sizes");
         if (n == 0) return;
         if (n > 0x7fffffff) fail(QST_ERR_INVALID, "too many rows");
-        // the source rows are those idx names; only their memory type is checked
         const int dev = current_device();
-        check_device_buffer(x, static_cast<size_t>(width) * sizeof(uint16_t), dev, "x");
-        check_device_buffer(y, sizeof(float), dev, "y");
+        check_device_buffer(x, static_cast<size_t>(n_rows) * width * sizeof(uint16_t), dev, "x");
+        check_device_buffer(y, static_cast<size_t>(n_rows) * sizeof(float), dev, "y");
         check_device_buffer(idx, static_cast<size_t>(n) * sizeof(int64_t), dev, "idx");
         check_device_buffer(xo, static_cast<size_t>(n) * width * sizeof(uint16_t), dev, "xo");
         check_device_buffer(yo, static_cast<size_t>(n) * sizeof(float), dev, "yo");
-        hipLaunchKernelGGL(qst::k_gather_rows, dim3(static_cast<unsigned>(n)), dim3(256), 0,
-                           static_cast<hipStream_t>(stream), x, width, y, idx, n, xo, yo);
+        // every index must name a row of x and y: checked on the host before
+        // the gather is queued, after the work already on the stream (which
+        // may be writing idx)
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        std::vector<int64_t> host(static_cast<size_t>(n));
+        hip_check(hipStreamSynchronize(s), "gather synchronize");
+        hip_check(hipMemcpy(host.data(), idx, sizeof(int64_t) * host.size(), hipMemcpyDeviceToHost), "idx copy");
+        for (int64_t k = 0; k < n; ++k)
+            if (host[k] < 0 || host[k] >= n_rows)
+                fail(QST_ERR_INVALID, "idx[" + std::to_string(k) + "] = " + std::to_string(host[k]) +
+                                          " is not a row index in [0, " + std::to_string(n_rows) + ")");
+        hipLaunchKernelGGL(qst::k_gather_rows, dim3(static_cast<unsigned>(n)), dim3(256), 0, s, x, width, y, idx, n,
+                           xo, yo);
         hip_check(hipGetLastError(), "gather launch");
     });
 }

@@ -56,7 +56,7 @@ class _RunDesc(C.Structure):
                 ("trace_llprop", C.c_void_p), ("trace_logu", C.c_void_p), ("trace_accept", C.c_void_p),
                 ("record_every", C.c_int32), ("record_chains", C.c_int32), ("record_buf", C.c_void_p),
                 ("pair_every", C.c_int32), ("pair_chains", C.c_int32), ("pair_x", C.c_void_p),
-                ("pair_ll", C.c_void_p), ("stream", C.c_void_p)]
+                ("pair_ll", C.c_void_p), ("stream", C.c_void_p), ("chain_offset", C.c_int64)]
 
 
 class _RunStats(C.Structure):
@@ -105,7 +105,7 @@ def lib():
         L.qst_mlp_predict.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.qst_mlp_surrogate.argtypes = [vp, C.POINTER(_Surrogate)]
         L.qst_mlp_targets.argtypes = [vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
-        L.qst_gather_rows.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, vp, vp, vp]
+        L.qst_gather_rows.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, C.c_int64, vp, vp, vp]
         L.qst_free_problem.argtypes = [vp]
         L.qst_free_problem.restype = None
         L.qst_last_error.restype = C.c_char_p
@@ -158,7 +158,15 @@ def _dev_tensor(t, dtypes, name):
         raise QstError(QST_ERR_INVALID, f"{name} must have dtype {' or '.join(dtypes)}, not {t.dtype}")
 
 
-def _check_run_buffers(trace, record, pairs):
+def _need(t, count, name):
+    """The library writes `count` elements through t's pointer: refuse a
+    shorter tensor (the library's own check only sees the end of the
+    allocation, which for a torch tensor is the caching allocator's block)."""
+    if t is not None and t.numel() < count:
+        raise QstError(QST_ERR_INVALID, f"{name} holds {t.numel()} elements; the call writes {count}")
+
+
+def _check_run_buffers(trace, record, pairs, cfg=None, D2=None, width=None):
     trace, record, pairs = trace or {}, record or {}, pairs or {}
     _dev_tensor(trace.get("llprop"), ("float64",), "trace llprop")
     _dev_tensor(trace.get("logu"), ("float64",), "trace logu")
@@ -166,6 +174,19 @@ def _check_run_buffers(trace, record, pairs):
     _dev_tensor(record.get("buf"), ("float64",), "record buf")
     _dev_tensor(pairs.get("x"), ("bfloat16", "int16", "uint16"), "pairs x")
     _dev_tensor(pairs.get("ll"), ("float64",), "pairs ll")
+    if cfg is None:
+        return
+    R, T = cfg.n_chains, cfg.n_steps
+    tc = min(trace.get("chains", 0), R)
+    for k in ("llprop", "logu", "accept"):
+        _need(trace.get(k), tc * T, f"trace {k}")
+    if record.get("every", 0) > 0 and record.get("chains", 0) > 0:
+        _need(record.get("buf"), min(record["chains"], R) * (T // record["every"]) * D2, "record buf")
+    if pairs.get("every", 0) > 0 and pairs.get("chains", 0) > 0:
+        slots, pc = T // pairs["every"], pairs["chains"]
+        rows = (slots - 1) * pc + min(pc, R) if slots > 0 else 0
+        _need(pairs.get("x"), rows * width, "pairs x")
+        _need(pairs.get("ll"), rows, "pairs ll")
 
 
 def _f64(a):
@@ -191,6 +212,7 @@ class RunConfig:
     adapt_factor: float = 1.1
     adapt_until: int = -1
     resume: bool = False
+    chain_offset: int = 0
 
 
 class Problem:
@@ -254,7 +276,7 @@ class Problem:
                         _dptr(trace.get("accept")), record.get("every", 0), record.get("chains", 0),
                         _dptr(record.get("buf")), pairs.get("every", 0), pairs.get("chains", 0),
                         _dptr(pairs.get("x")), _dptr(pairs.get("ll")),
-                        stream if stream is not None else current_stream())
+                        stream if stream is not None else current_stream(), cfg.chain_offset)
 
     def run(self, cfg: RunConfig, trace=None, record=None, stats=True, stream=None, surrogate=None, pairs=None):
         """qst_run_chains on this problem alone.  trace: dict(chains=k, llprop=,
@@ -264,7 +286,7 @@ class Problem:
         chains=, x= bfloat16 [n_steps // every, chains, pair_width], ll= float64
         [n_steps // every, chains]): the proposal of step (s + 1) * every of
         chain c and its log L in row s * chains + c."""
-        _check_run_buffers(trace, record, pairs)
+        _check_run_buffers(trace, record, pairs, cfg, self.D * self.D, self.pair_width)
         rd = self._run_desc(cfg, trace, record, stream, surrogate, pairs)
         arr = (C.c_void_p * 1)(self._h)
         st = _RunStats()
@@ -316,6 +338,8 @@ class Problem:
         _dev_tensor(rho_dev, ("complex128", "float64"), "rho")
         _dev_tensor(out_dev, ("float64",), "out")
         n = out_dev.numel()
+        D2 = self.D * self.D
+        _need(rho_dev, n * D2 * (1 if rho_dev.is_complex() else 2), "rho")
         _check(lib().qst_loglik(self._h, C.c_void_p(rho_dev.data_ptr()), n, C.c_void_p(out_dev.data_ptr()),
                                 _PATH[path], _PREC[precision],
                                 stream if stream is not None else current_stream()))
@@ -374,6 +398,9 @@ class Mlp:
         _dev_tensor(x_bf16, ("bfloat16",), "x")
         _dev_tensor(y_f32, ("float32",), "y")
         n = x_bf16.shape[0] if rows is None else rows
+        if offset < 0 or offset + n > x_bf16.shape[0] or offset + n > y_f32.numel():
+            raise QstError(QST_ERR_INVALID, f"rows [{offset}, {offset + n}) exceed x ({x_bf16.shape[0]} rows) "
+                                            f"or y ({y_f32.numel()} values)")
         xp = x_bf16.data_ptr() + offset * x_bf16.shape[1] * 2
         yp = y_f32.data_ptr() + offset * 4
         loss = C.c_float()
@@ -399,6 +426,7 @@ def standardise_targets(ll_dev, y_dev, stream=None):
     """qst_mlp_targets: y = (ll - mean) / sd on the device; returns (mean, sd)."""
     _dev_tensor(ll_dev, ("float64",), "ll")
     _dev_tensor(y_dev, ("float32",), "y")
+    _need(y_dev, ll_dev.numel(), "y")
     mean, sd = C.c_double(), C.c_double()
     _check(lib().qst_mlp_targets(C.c_void_p(ll_dev.data_ptr()), ll_dev.numel(), C.c_void_p(y_dev.data_ptr()),
                                  C.byref(mean), C.byref(sd), stream if stream is not None else current_stream()))
@@ -410,8 +438,12 @@ def gather_rows(x, y, idx, xo, yo, stream=None):
     for t, dt, name in ((x, ("bfloat16",), "x"), (y, ("float32",), "y"), (idx, ("int64",), "idx"),
                         (xo, ("bfloat16",), "xo"), (yo, ("float32",), "yo")):
         _dev_tensor(t, dt, name)
-    _check(lib().qst_gather_rows(C.c_void_p(x.data_ptr()), x.shape[1], C.c_void_p(y.data_ptr()),
-                                 C.c_void_p(idx.data_ptr()), idx.numel(), C.c_void_p(xo.data_ptr()),
+    n_rows, n = x.shape[0], idx.numel()
+    _need(y, n_rows, "y")
+    _need(xo, n * x.shape[1], "xo")
+    _need(yo, n, "yo")
+    _check(lib().qst_gather_rows(C.c_void_p(x.data_ptr()), x.shape[1], C.c_void_p(y.data_ptr()), n_rows,
+                                 C.c_void_p(idx.data_ptr()), n, C.c_void_p(xo.data_ptr()),
                                  C.c_void_p(yo.data_ptr()), stream if stream is not None else current_stream()))
 
 
@@ -441,8 +473,8 @@ def run_batch(problems, configs, stats=True, stream=None, traces=None):
     Problem.run)."""
     n = len(problems)
     traces = traces or [None] * n
-    for t in traces:
-        _check_run_buffers(t, None, None)
+    for p, c, t in zip(problems, configs, traces):
+        _check_run_buffers(t, None, None, c, p.D * p.D, p.pair_width)
     rds = (_RunDesc * n)(*[p._run_desc(c, t, None, stream) for p, c, t in zip(problems, configs, traces)])
     hs = (C.c_void_p * n)(*[p._h for p in problems])
     st = (_RunStats * n)()

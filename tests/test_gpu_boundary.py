@@ -100,3 +100,51 @@ def test_binding_refuses_bad_tensors():
     # a good run still goes through
     st = P.run(cfg)
     assert st["proposed"] == 8 * 4
+
+
+def test_binding_refuses_a_tensor_one_row_short():
+    """A tensor carved by torch's caching allocator lies inside a larger
+    block, so the library's allocation-extent check cannot see that it is
+    short; the binding compares the element count with what the call writes
+    and raises before anything is queued."""
+    prob = synth.make_problem("c2")
+    P = qst.Problem(2, prob.counts)
+    R, T = 16, 8
+    cfg = qst.RunConfig(n_chains=R, n_steps=T, seed=1)
+    short = dict(chains=R, llprop=torch.zeros((R - 1, T), dtype=torch.float64, device="cuda"))
+    with pytest.raises(qst.QstError) as e:
+        P.run(cfg, trace=short)
+    assert e.value.status == qst.QST_ERR_INVALID and "trace llprop" in str(e.value)
+    rec = dict(every=2, chains=4, buf=torch.zeros((4, T // 2 - 1, 4, 4), dtype=torch.float64, device="cuda"))
+    with pytest.raises(qst.QstError) as e:
+        P.run(cfg, record=rec)
+    assert e.value.status == qst.QST_ERR_INVALID and "record buf" in str(e.value)
+    rho = torch.zeros((2, 4, 4, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(qst.QstError) as e:
+        P.loglik(rho[:1], torch.zeros(2, dtype=torch.float64, device="cuda"))
+    assert e.value.status == qst.QST_ERR_INVALID and "rho" in str(e.value)
+    # nothing was launched: the handle has not run yet
+    with pytest.raises(qst.QstError) as e:
+        P.pool()
+    assert e.value.status == qst.QST_ERR_STATE
+    ok = dict(chains=R, llprop=torch.zeros((R, T), dtype=torch.float64, device="cuda"))
+    assert P.run(cfg, trace=ok)["proposed"] == R * T
+
+
+def test_gather_rows_checks_every_index():
+    n_rows, width = 40, 32
+    x = torch.arange(n_rows * width, device="cuda").to(torch.bfloat16).reshape(n_rows, width)
+    y = torch.arange(n_rows, dtype=torch.float32, device="cuda")
+    xo = torch.zeros((3, width), dtype=torch.bfloat16, device="cuda")
+    yo = torch.zeros(3, dtype=torch.float32, device="cuda")
+    for bad in ([0, n_rows, 1], [5, -1, 2]):
+        idx = torch.tensor(bad, dtype=torch.int64, device="cuda")
+        with pytest.raises(qst.QstError) as e:
+            qst.gather_rows(x, y, idx, xo, yo)
+        assert e.value.status == qst.QST_ERR_INVALID and "is not a row index" in str(e.value)
+    assert float(yo.abs().sum()) == 0.0        # nothing was written
+    idx = torch.tensor([n_rows - 1, 0, 7], dtype=torch.int64, device="cuda")
+    qst.gather_rows(x, y, idx, xo, yo)
+    torch.cuda.synchronize()
+    assert yo.cpu().tolist() == [n_rows - 1, 0, 7]
+    assert torch.equal(xo.cpu(), x[[n_rows - 1, 0, 7]].cpu())

@@ -106,10 +106,12 @@ def test_fullsize_c4_sampled_chains():
     ll0 = ch.ll.copy()
     o = ch.run(NT)
     g_ll = tr["llprop"].cpu().numpy()
+    g_acc = tr["accept"].cpu().numpy()
     stop = first_near_step(o["trace_llprop"], g_ll, o["trace_logu"], ll0, o["trace_accept"])
     for r in range(k):
         s = stop[r]
         assert np.all(np.abs(o["trace_llprop"][r, :s] - g_ll[r, :s]) <= 1e-10 * np.abs(o["trace_llprop"][r, :s]))
+        assert np.array_equal(o["trace_accept"][r, :s], g_acc[r, :s]), r
         if s == NT:
             assert np.allclose(x[r], ch.x[r], rtol=1e-9, atol=1e-9)
     last = O.Chains(Q, prob.counts, O.RunParams(n_chains=1, n_steps=0, seed=prob.seed, beta0=beta, adapt_every=100,
@@ -120,8 +122,8 @@ def test_fullsize_c4_sampled_chains():
 
 
 def test_fullsize_mixed_batch_sampled():
-    """The 256-problem mixed batch (1..6 qubits, 256..4096 chains each) in one
-    launch, as bench.py runs it (20 steps): for one problem of every qubit
+    """The 256-problem mixed batch (1..6 qubits, 256..4096 chains each) in the
+    batch call bench.py times, over 20 steps: for one problem of every qubit
     count, its first and last chain (the last one only at 6 qubits) replayed
     by the oracle."""
     probs = synth.mixed_batch(256)
