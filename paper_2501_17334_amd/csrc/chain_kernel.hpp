@@ -58,8 +58,14 @@ struct ChainArgs {
     const double* ndv;      // [KD] counts, task-major order of the likelihood transforms (LikSplit)
     const uint16_t* muv;    // [KD] Pauli indices in the same order
     const void* mfrag;      // dense path: the Pauli matrix in MFMA fragment order
-    int64_t R;              // chains of this handle
-    int64_t chain0;         // problem-wide index of chain 0 (its Philox counter word)
+    // Chains c < R.  The chain kernels use problem-wide indices c in
+    // [chain0, R) with chain0 the handle's chain offset (a kernel argument of
+    // its own): the host passes every per-chain array (and the trace and
+    // record buffers) shifted back by chain0 rows, so that row c is chain c's,
+    // and the trace/record bounds as problem-wide indices; c is also the
+    // Philox counter word.  Delayed acceptance passes unshifted arrays and
+    // local indices in [0, R), and adds its chain0 for the counter word.
+    int64_t R;
     double* x;              // [R][d] current state
     double* ll;             // [R] log L of the current state
     double* beta;           // [R]
@@ -1295,9 +1301,9 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     const int tid = threadIdx.x;
     const int team = tid / G;
     const int lane = tid % G;
-    const int64_t chain = tile_chain0 + team;
+    const int64_t chain = tile_chain0 + team;     // problem-wide index
     const bool live = chain < A.R;
-    const int64_t c = live ? chain : 0;
+    const int64_t c = live ? chain : A.R - 1;     // a valid row for the loads of idle teams
 
     const LogEntry* logtab = reinterpret_cast<const LogEntry*>(tables);
     double* base = lds + team * S::kLdsChain;
@@ -1320,7 +1326,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         const bool normal = job < NB;
         const uint64_t c0 = normal ? static_cast<uint64_t>(job) : 0;
         const uint64_t c3 = normal ? 0 : (static_cast<uint64_t>(kTagMH) << 56);
-        const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(A.chain0 + c), c3, A.seed, 0);
+        const Block4 B = philox4x64_10(c0, step, static_cast<uint64_t>(c), c3, A.seed, 0);
         if (normal) {
             box_muller(B.w[0], B.w[1], v[0], v[1], logtab);
             box_muller(B.w[2], B.w[3], v[2], v[3], logtab);
@@ -1599,12 +1605,12 @@ constexpr int chain_min_waves()
 }
 
 template <int Q, int G, int WG, int PATH = kPathKron, int PREC = kPrecF64, int PARAM = kParamGamma>
-__global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainArgs A)
+__global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainArgs A, int64_t chain0)
 {
     extern __shared__ double lds[];
     wg_tables_init<Q, PATH>(lds, threadIdx.x, WG);
     __syncthreads();
-    chain_tile<Q, G, WG, PATH, PREC, PARAM>(A, static_cast<int64_t>(blockIdx.x) * (WG / G), lds,
+    chain_tile<Q, G, WG, PATH, PREC, PARAM>(A, chain0 + static_cast<int64_t>(blockIdx.x) * (WG / G), lds,
                                             lds + WgTables<Q, PATH>::kDoubles);
 }
 

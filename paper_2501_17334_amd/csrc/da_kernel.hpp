@@ -34,6 +34,7 @@ struct DaArgs {
     double* u_da;           // [R] uniform of stage 1
     int32_t* surv;          // [R] chains that passed stage 1
     int32_t* n_surv;        // [1]
+    int64_t chain0;         // the handle's chain offset (local chain c draws the numbers of chain0 + c)
     int64_t j;              // global index of the step (1-based)
     int64_t t;              // its index within this call
 };
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(WG) void k_da_propose(DaArgs P)
             const bool normal = job < NB;
             const uint64_t c0 = normal ? static_cast<uint64_t>(job) : 0;
             const uint64_t tag = normal ? kTagNormal : (job == NB ? kTagMH : kTagDA);
-            const Block4 B = philox4x64_10(c0, static_cast<uint64_t>(P.j), static_cast<uint64_t>(A.chain0 + c), tag << 56,
+            const Block4 B = philox4x64_10(c0, static_cast<uint64_t>(P.j), static_cast<uint64_t>(P.chain0 + c), tag << 56,
                                            A.seed, 0);
             if (normal) {
                 double n0, n1, n2, n3;

@@ -275,17 +275,18 @@ bool shape_compiled(int Q, Shape sh)
     return false;
 }
 
+// a.R is one past the last problem-wide chain index, chain0 the first (make_args)
 template <int Q, int G, int WG, int PATH, int PREC, int PARAM = qst::kParamGamma>
-void launch_chains_t(const qst::ChainArgs& a, hipStream_t s)
+void launch_chains_t(const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
 {
     using S = qst::TeamShape<Q, G, PATH, PARAM>;
     const int64_t teams = WG / G;
-    const int64_t blocks = (a.R + teams - 1) / teams;
+    const int64_t blocks = (a.R - chain0 + teams - 1) / teams;
     const size_t lds = (static_cast<size_t>(teams) * S::kLdsChain + qst::WgTables<Q, PATH>::kDoubles) * sizeof(double);
     allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC, PARAM>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many chains for one launch");
     hipLaunchKernelGGL((qst::k_chains<Q, G, WG, PATH, PREC, PARAM>), dim3(static_cast<unsigned>(blocks)), dim3(WG),
-                       lds, s, a);
+                       lds, s, a, chain0);
     hip_check(hipGetLastError(), "chain kernel launch");
 }
 
@@ -319,13 +320,13 @@ void launch_loglik_t(const double* nd, const uint16_t* mu, const double* ndv, co
 
 // Dirichlet(alpha) weights: the Kronecker route with the default team shape
 // of each qubit count.
-void launch_chains_dirichlet(int Q, int prec, const qst::ChainArgs& a, hipStream_t s)
+void launch_chains_dirichlet(int Q, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
 {
     using namespace qst;
 #define QST_DIR(q, g, wg)                                                                               \
     if (Q == q)                                                                                         \
-        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamDirichlet>(a, s) \
-                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamDirichlet>(a, s);
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamDirichlet>(a, chain0, s) \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamDirichlet>(a, chain0, s);
     QST_DIR(1, 8, 64) QST_DIR(2, 16, 64) QST_DIR(3, 32, 64) QST_DIR(4, 64, 256) QST_DIR(5, 256, 256)
     QST_DIR(6, 512, 512)
 #undef QST_DIR
@@ -334,24 +335,24 @@ void launch_chains_dirichlet(int Q, int prec, const qst::ChainArgs& a, hipStream
 
 // Algorithm 1 (the Bures draw): the Kronecker route with one fixed team
 // shape per qubit count (one wavefront per chain at 4 qubits).
-void launch_chains_bures(int Q, int prec, const qst::ChainArgs& a, hipStream_t s)
+void launch_chains_bures(int Q, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
 {
     using namespace qst;
 #define QST_BURES(q, g, wg)                                                                             \
     if (Q == q)                                                                                         \
-        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamBures>(a, s)     \
-                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamBures>(a, s);
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamBures>(a, chain0, s)     \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamBures>(a, chain0, s);
     QST_BURES(1, 8, 64) QST_BURES(2, 16, 64) QST_BURES(3, 32, 64) QST_BURES(4, 64, 256)
 #undef QST_BURES
     fail(QST_ERR_UNSUPPORTED, "Algorithm 1 (QST_PARAM_BURES) is built for 1..4 qubits");
 }
 
-void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a, hipStream_t s)
+void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
 {
     using namespace qst;
     if (path == kPathDense) {
 #define QST_DENSE(q, pr) \
-    if (Q == q && prec == pr) return launch_chains_t<q, 64, 1024, kPathDense, pr>(a, s);
+    if (Q == q && prec == pr) return launch_chains_t<q, 64, 1024, kPathDense, pr>(a, chain0, s);
         QST_DENSE(1, kPrecF64) QST_DENSE(1, kPrecF32) QST_DENSE(1, kPrecBF16x3)
         QST_DENSE(2, kPrecF64) QST_DENSE(2, kPrecF32) QST_DENSE(2, kPrecBF16x3)
         QST_DENSE(3, kPrecF64) QST_DENSE(3, kPrecF32) QST_DENSE(3, kPrecBF16x3)
@@ -361,8 +362,8 @@ void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a,
     }
 #define QST_CASE(q, g, wg)                                                                              \
     if (Q == q && sh.G == g && sh.WG == wg)                                                             \
-        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32>(a, s)                  \
-                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64>(a, s);
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32>(a, chain0, s)                  \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64>(a, chain0, s);
     QST_CASE(1, 8, 64) QST_CASE(1, 16, 64) QST_CASE(1, 64, 64)
     QST_CASE(2, 16, 64) QST_CASE(2, 32, 64) QST_CASE(2, 64, 64)
     QST_CASE(3, 32, 64) QST_CASE(3, 64, 64)
@@ -572,6 +573,10 @@ void validate_run(const qst_problem* p, const qst_run_desc& r)
         check_device_buffer(r.pair_ll, rows * sizeof(double), p->device, "pair_ll");
     }
     if (r.chain_offset < 0) fail(QST_ERR_INVALID, "chain_offset must be >= 0");
+    if (r.chain_offset > 0 && r.chain_offset + r.n_chains + r.trace_chains + r.record_chains > 0x7fffffff)
+        fail(QST_ERR_INVALID, "chain_offset + n_chains must stay below 2^31");
+    if (r.chain_offset > 0 && r.pair_every > 0 && r.pair_chains > 0)
+        fail(QST_ERR_UNSUPPORTED, "the pair recorder runs with chain_offset 0");
     if (r.resume) {
         if (!p->have_run) fail(QST_ERR_STATE, "resume requested before any run of this handle");
         if (r.n_chains != p->R) fail(QST_ERR_INVALID, "resume with a different n_chains");
@@ -733,7 +738,22 @@ void prepare_state(qst_problem* p, const qst_run_desc& r)
     }
 }
 
-qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
+template <typename T>
+T* rows_back(T* ptr, int64_t rows, int64_t width)
+{
+    // ptr moved back by `rows` rows of `width` elements (integer arithmetic:
+    // the kernels only touch rows chain0 and later, inside the buffer)
+    if (!ptr) return ptr;
+    return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(ptr) -
+                                static_cast<uintptr_t>(rows) * static_cast<uintptr_t>(width) * sizeof(T));
+}
+
+// Arguments of the chain kernels.  problem_wide (the chain and batch
+// kernels): chains are addressed by their index within the problem, c in
+// [chain_offset, chain_offset + R), and every per-chain buffer is passed
+// shifted back by chain_offset rows; otherwise (delayed acceptance) local
+// indices in [0, R).
+qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r, bool problem_wide = true)
 {
     qst::ChainArgs a{};
     a.nd = p->nd;
@@ -742,7 +762,6 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
     a.muv = p->muv;
     a.mfrag = p->path == QST_PATH_DENSE ? p->fragments(p->precision) : nullptr;
     a.R = p->R;
-    a.chain0 = p->chain0;
     a.x = p->x;
     a.ll = p->ll;
     a.beta = p->beta;
@@ -779,6 +798,28 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r)
     a.pair_width = p->da_width();
     a.pair_x = r.pair_x;
     a.pair_ll = r.pair_ll;
+    if (problem_wide && p->chain0 != 0) {
+        const int64_t g = p->chain0;
+        const int64_t n_rec = r.record_every > 0 ? r.n_steps / r.record_every : 0;
+        a.R = g + p->R;
+        a.x = rows_back(a.x, g, p->d);
+        a.ll = rows_back(a.ll, g, 1);
+        a.beta = rows_back(a.beta, g, 1);
+        a.acc_win = rows_back(a.acc_win, g, 1);
+        a.rho_cur = rows_back(a.rho_cur, g, p->D2);
+        a.s1 = rows_back(a.s1, g, p->D2);
+        a.s2 = rows_back(a.s2, g, p->D2);
+        a.n_stored = rows_back(a.n_stored, g, 1);
+        a.n_acc = rows_back(a.n_acc, g, 1);
+        a.n_near = rows_back(a.n_near, g, 1);
+        a.trace_chains = static_cast<int32_t>(g + r.trace_chains);
+        a.tr_ll = rows_back(a.tr_ll, g, r.n_steps);
+        a.tr_lu = rows_back(a.tr_lu, g, r.n_steps);
+        a.tr_acc = rows_back(a.tr_acc, g, r.n_steps);
+        a.record_chains = static_cast<int32_t>(g + r.record_chains);
+        a.rec = rows_back(a.rec, g, n_rec * p->D2);
+        // the pair recorder runs with chain_offset 0 (validate_run)
+    }
     return a;
 }
 
@@ -873,7 +914,7 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
         const int per = qst::batch_wg(qst::batch_class(p->Q)) / batch_team(p->Q);
         const int32_t prec = p->precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64;
         for (int64_t c0 = 0; c0 < p->R; c0 += per) {
-            items.push_back({i, p->Q, c0, prec, 0});
+            items.push_back({i, p->Q, p->chain0 + c0, prec, 0});   // problem-wide chain index (make_args)
             cost.push_back(chain_step_cost(p->Q) * static_cast<double>(std::min<int64_t>(per, p->R - c0)) *
                            static_cast<double>(std::max<int64_t>(runs[i].n_steps, 1)));
         }
@@ -970,12 +1011,12 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
             qst_problem* p = problems[0];
             const qst::ChainArgs a = make_args(p, runs[0]);
             if (p->param == QST_PARAM_BURES)
-                launch_chains_bures(p->Q, static_cast<int>(p->precision), a, s);
+                launch_chains_bures(p->Q, static_cast<int>(p->precision), a, p->chain0, s);
             else if (p->param == QST_PARAM_DIRICHLET)
-                launch_chains_dirichlet(p->Q, static_cast<int>(p->precision), a, s);
+                launch_chains_dirichlet(p->Q, static_cast<int>(p->precision), a, p->chain0, s);
             else
                 launch_chains(p->Q, current_shape(p->Q), p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
-                              static_cast<int>(p->precision), a, s);
+                              static_cast<int>(p->precision), a, p->chain0, s);
         } else {
             for (int i = 0; i < n_problems; ++i)
                 if (runs[i].surrogate) fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs one problem per call");
@@ -1624,7 +1665,7 @@ void launch_da(qst_problem* p, const qst_run_desc& r, hipStream_t s)
         r0.n_steps = 0;
         r0.surrogate = nullptr;
         qst::ChainArgs a0 = make_args(p, r0);
-        launch_chains(p->Q, sh, qst::kPathKron, qst::kPrecF64, a0, s);
+        launch_chains(p->Q, sh, qst::kPathKron, qst::kPrecF64, a0, p->chain0, s);
     }
     const int dp = p->da_width();
     hipLaunchKernelGGL(qst::k_rows_to_bf16, dim3(blocks_for(p->R * dp, 256)), dim3(256), 0, s, p->x, p->R, p->d, dp,
@@ -1636,7 +1677,8 @@ void launch_da(qst_problem* p, const qst_run_desc& r, hipStream_t s)
     fill_zero(p->nnear, p->R, s);
     hip_check(hipGetLastError(), "delayed-acceptance setup");
     qst::DaArgs P{};
-    P.A = make_args(p, r);
+    P.A = make_args(p, r, false);   // local chain indices; the propose kernel adds chain0
+    P.chain0 = p->chain0;
     P.s_cur = p->s_cur;
     P.n_stage1 = p->n_stage1;
     P.yprop = p->yprop;

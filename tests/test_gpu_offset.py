@@ -47,3 +47,47 @@ def test_tail_of_a_run_alone(name, R, T, k):
     one.run(T)
     assert np.allclose(xt[-1], one.x[0], rtol=1e-9, atol=1e-9)
     assert abs(lt[-1] - one.ll[0]) <= 1e-10 * abs(one.ll[0])
+
+
+def _buffers(n_tr, n_rec, T, every, D):
+    tr = dict(chains=n_tr, llprop=torch.full((n_tr, T), float("nan"), dtype=torch.float64, device="cuda"),
+              logu=torch.zeros((n_tr, T), dtype=torch.float64, device="cuda"),
+              accept=torch.zeros((n_tr, T), dtype=torch.int8, device="cuda"))
+    rec = dict(every=every, chains=n_rec,
+               buf=torch.zeros((n_rec, T // every, D, D), dtype=torch.float64, device="cuda"))
+    return tr, rec
+
+
+def test_offset_run_traces_and_records():
+    """Traces and records of a range of chains are the rows of a full run's."""
+    prob = synth.make_problem("c2")
+    R, T, k, every = 256, 300, 100, 10
+    cfg = dict(n_steps=T, seed=prob.seed, beta0=0.05, adapt_every=50)
+    full = qst.Problem(2, prob.counts)
+    trf, recf = _buffers(R, 200, T, every, 4)
+    full.run(qst.RunConfig(n_chains=R, **cfg), trace=trf, record=recf)
+    tail = qst.Problem(2, prob.counts)
+    trt, rect = _buffers(R - k - 6, 200 - k, T, every, 4)
+    tail.run(qst.RunConfig(n_chains=R - k, chain_offset=k, **cfg), trace=trt, record=rect)
+    torch.cuda.synchronize()
+    for key in ("llprop", "logu", "accept"):
+        assert torch.equal(trf[key][k:R - 6], trt[key]), key
+    assert torch.equal(recf["buf"][k:200], rect["buf"])
+
+
+def test_offset_handle_in_a_batch():
+    probs = [synth.make_problem(n) for n in ("c1", "c3", "c2")]
+    offs = [5, 70, 0]
+    Rs = [40, 30, 50]
+    cfgs = [qst.RunConfig(n_chains=R, n_steps=25, seed=p.seed, beta0=0.03, chain_offset=o)
+            for p, R, o in zip(probs, Rs, offs)]
+    hs = [qst.Problem(p.n_qubits, p.counts) for p in probs]
+    qst.run_batch(hs, cfgs)
+    for p, R, o, h in zip(probs, Rs, offs, hs):
+        full = qst.Problem(p.n_qubits, p.counts)
+        full.run(qst.RunConfig(n_chains=o + R, n_steps=25, seed=p.seed, beta0=0.03))
+        xf, lf, _, _ = full.state()
+        xb, lb, _, _ = h.state()
+        # the batch runs the 4-qubit problem with its batch team size: equal up to rounding
+        assert np.allclose(xf[o:], xb, rtol=1e-12, atol=1e-12), p.name
+        assert np.allclose(lf[o:], lb, rtol=1e-12), p.name
