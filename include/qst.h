@@ -257,6 +257,23 @@ qst_status qst_list_launch_shapes(int32_t n_qubits, int32_t* teams, int32_t* wor
 qst_status qst_pool_moments(const qst_problem* p, double* mean, double* second, double* se,
                             int64_t* n_samples);
 
+/* Eq. (BME2) as qst_pool_moments computes it (the same kernels and summation
+ * order, so the same bits), for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Allocates nothing and does not wait: both passes are queued
+ * on `stream` (hipStream_t; NULL = default stream), which the caller orders
+ * after the handle's run.  out: DEVICE, 6 D^2 doubles = mean (D*D*2
+ * interleaved complex), second moments (D*D*2, as in qst_pool_moments),
+ * between-chain standard errors (D*D*2); n_out: DEVICE, one int64, the total
+ * number of stored samples (0 leaves NaN in out).  The partial sums live in
+ * a static device array of the library, 16 MiB per GPU it runs on, held
+ * until the process ends: QST_ERR_INVALID if ceil(R / 256) * (5 D^2 * 8 + 8)
+ * bytes (plus alignment) exceed it, i.e. beyond about 419,000 chains at 4
+ * qubits or 26,000 at 6.  Every call on one GPU shares that array, so calls
+ * that overlap on one GPU (other streams, other threads) race on it.
+ * QST_ERR_STATE before any run. */
+qst_status qst_pool_moments_static(const qst_problem* p, double* out, int64_t* n_out, void* stream);
+
 /* Copy the chains' current state to HOST buffers (NULL to skip):
  * x [R][d], loglik [R], beta [R], n_stored [R].  Waits for the last run. */
 qst_status qst_chain_state(const qst_problem* p, double* x, double* loglik, double* beta,

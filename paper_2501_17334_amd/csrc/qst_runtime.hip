@@ -412,6 +412,34 @@ void launch_loglik(int Q, int prec, const double* nd, const uint16_t* mu, const 
     return launch_loglik_p<qst::kPrecF64>(Q, nd, mu, ndv, muv, rho, n, out, s);
 }
 
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free pooling call (qst_pool_moments_static):
+// one file-scope array per device for the partial sums of the fixed-order
+// reduction.  In host code `scratch` only names the symbol; its device
+// address, per device, comes from hipGetSymbolAddress at set-up (the first
+// qst_init_problem on that device) and is the only way host code refers to it.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// With `dev` current: look up (once) and return its copy of `scratch`.
+void* scratch_address(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) fail(QST_ERR_UNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) fail(QST_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 struct DeviceGuard {
     int prev = 0;
     explicit DeviceGuard(int dev)
@@ -661,6 +689,7 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
             nd[i] = static_cast<double>(p->counts[i]);
         }
         DeviceGuard g(p->device);
+        (void)scratch_address(p->device);   // set-up of the allocation-free pooling call
         p->nd = dev_alloc<double>(p->KD);
         hip_check(hipMemcpy(p->nd, nd.data(), sizeof(double) * p->KD, hipMemcpyHostToDevice), "copy counts");
         // mu(k, t) = sum_q [t_q] (s_q(k) + 1) 4^(Q-1-q): the Pauli string whose
@@ -1128,6 +1157,40 @@ qst_status qst_pool_moments(const qst_problem* p, double* mean, double* second, 
         dev_free(nsum);
         dev_free(outd);
         dev_free(nout);
+    });
+}
+
+qst_status qst_pool_moments_static(const qst_problem* p, double* out, int64_t* n_out, void* stream)
+{
+    return guarded([&] {
+        if (!p) fail(QST_ERR_INVALID, "NULL handle");
+        if (!p->have_run) fail(QST_ERR_STATE, "pool before any run");
+        if (!out || !n_out) fail(QST_ERR_INVALID, "NULL output");
+        const int64_t chunk = 256;
+        const int64_t nchunks = (p->R + chunk - 1) / chunk;
+        const size_t part_doubles = static_cast<size_t>(nchunks) * 5 * p->D2;
+        // partial sums, then the per-chunk sample counts at the next 256-byte boundary
+        const size_t nsum_off = (part_doubles * sizeof(double) + 255) / 256 * 256;
+        const size_t need = nsum_off + static_cast<size_t>(nchunks) * sizeof(int64_t);
+        if (need > kScratchBytes)
+            fail(QST_ERR_INVALID, "pooling " + std::to_string(p->R) + " chains of " + std::to_string(p->Q) +
+                                      " qubits needs " + std::to_string(need) + " bytes of scratch; the static "
+                                      "scratch holds " + std::to_string(kScratchBytes) +
+                                      " (use qst_pool_moments)");
+        check_device_buffer(out, static_cast<size_t>(6) * p->D2 * sizeof(double), p->device, "out");
+        check_device_buffer(n_out, sizeof(int64_t), p->device, "n_out");
+        DeviceGuard g(p->device);
+        char* base = static_cast<char*>(scratch_address(p->device));
+        double* part = reinterpret_cast<double*>(base);
+        int64_t* nsum = reinterpret_cast<int64_t*>(base + nsum_off);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // both passes write every scratch entry they read: nothing to clear
+        hipLaunchKernelGGL(qst::k_pool_partial, dim3(static_cast<unsigned>(nchunks)), dim3(qst::kPoolThreads), 0, s,
+                           p->s1, p->s2, p->nst, p->R, p->D2, chunk, part, nsum);
+        hip_check(hipGetLastError(), "pool partial launch");
+        hipLaunchKernelGGL(qst::k_pool_final, dim3((p->D2 + qst::kPoolThreads - 1) / qst::kPoolThreads),
+                           dim3(qst::kPoolThreads), 0, s, part, nsum, static_cast<int>(nchunks), p->D, out, n_out);
+        hip_check(hipGetLastError(), "pool final launch");
     });
 }
 
