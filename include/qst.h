@@ -78,11 +78,13 @@ typedef enum {
  * mode; the chain state, rho and the moments are FP64 in every mode. */
 typedef enum {
     QST_FP64 = 0,     /* exact FP64 */
-    QST_FP32 = 1,     /* dense: FP32 operands and accumulation, log p in FP64;
+    QST_FP32 = 1,     /* dense: FP32 operands and accumulation, log2 p by the
+                         hardware FP32 logarithm, FP64 sum;
                          Kronecker: FP32 Pauli coefficients, transforms and log2 p
                          (hardware logarithm, p clamped at 2^-126), FP64 sum */
     QST_BF16X3 = 2    /* dense only: vec(rho) split into three BF16 parts against
-                         the exact BF16 M, FP32 accumulation, log p in FP64 */
+                         the exact BF16 M, FP32 accumulation, log2 p in FP32 as
+                         for QST_FP32, FP64 sum */
 } qst_precision;
 
 /* How p_kl = Tr(Lambda_kl rho) is formed. */
@@ -138,6 +140,16 @@ typedef struct {
     const double* povm;
     int32_t n_povm;
     double alpha;            /* QST_PARAM_DIRICHLET: concentration alpha > 0 (ignored otherwise) */
+    /* Optional Poisson counts (NULL: the multinomial likelihood of Eq.
+     * (likelihood)).  intensity: host, one value lambda_m >= 0 per count
+     * (3^Q 2^Q, or n_povm with povm), copied: count m is Poisson with mean
+     * lambda_m p_m, independently of the others (a non-multinomial
+     * likelihood; Section "Proposed Approach" confines such a change to the
+     * likelihood steps of Algorithm 2), so up to a constant
+     * log L = sum_{c_m > 0} c_m log p_m - sum_m lambda_m p_m, the second sum
+     * evaluated in FP64 as Tr(rho Lambda), Lambda = sum_m lambda_m Pi_m.
+     * Every path and precision; QST_ERR_UNSUPPORTED with a surrogate. */
+    const double* intensity;
 } qst_problem_desc;
 
 /* Frozen MLP surrogate s(x) of log L for delayed acceptance (Christen & Fox

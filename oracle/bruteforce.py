@@ -14,8 +14,22 @@ import numpy as np
 from . import oracle as O
 
 
-def posterior_mean_is(Q, counts, n_draws, seed, batch=1 << 20):
-    """Returns (mean packed rho, standard error packed, IS effective size)."""
+def _trace_with(packed, lam):
+    """Tr(rho Lambda) for a batch of packed rho [n, D, D] and a Hermitian D x D
+    Lambda, from Re rho_ab (a <= b) and Im rho_ba (a > b)."""
+    D = lam.shape[0]
+    iu = np.triu_indices(D, 1)
+    tot = np.einsum("naa,aa->n", packed, lam.real)
+    # off-diagonal pairs (a < b): 2 Re(rho_ab conj(Lambda_ab)) = 2 (Re rho Re L + Im rho Im L)
+    re = packed[:, iu[0], iu[1]]
+    im = packed[:, iu[1], iu[0]]
+    return tot + 2.0 * (re @ lam.real[iu] + im @ lam.imag[iu])
+
+
+def posterior_mean_is(Q, counts, n_draws, seed, batch=1 << 20, poisson_lambda=None):
+    """Returns (mean packed rho, standard error packed, IS effective size).
+    poisson_lambda (D x D, Hermitian): Poisson counts, whose log L is the
+    multinomial one minus Tr(rho Lambda) with Lambda = sum_m lambda_m Pi_m."""
     D, _, d = O.dims(Q)
     rng = np.random.default_rng(seed)
     lls, rhos = [], []
@@ -24,6 +38,8 @@ def posterior_mean_is(Q, counts, n_draws, seed, batch=1 << 20):
         n = min(batch, n_draws - done)
         xs = rng.standard_normal((n, d))
         ll, rp = O.eval_batch(Q, counts, xs, want_rho=True)
+        if poisson_lambda is not None:
+            ll = ll - _trace_with(rp, np.asarray(poisson_lambda))
         lls.append(ll)
         rhos.append(rp.reshape(n, D * D))
         done += n

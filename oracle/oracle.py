@@ -40,7 +40,8 @@ class _RunDesc(C.Structure):
                 ("adapt_factor", C.c_double), ("adapt_until", C.c_int64), ("seed", C.c_uint64),
                 ("surrogate", C.POINTER(_Mlp)), ("trace_chains", C.c_int32),
                 ("record_every", C.c_int32), ("record_chains", C.c_int32), ("param", C.c_int32),
-                ("povm", c_double_p), ("n_povm", C.c_int32), ("alpha", C.c_double)]
+                ("povm", c_double_p), ("n_povm", C.c_int32), ("alpha", C.c_double),
+                ("intensity", c_double_p)]
 
 
 class _State(C.Structure):
@@ -82,6 +83,8 @@ def lib():
         L.orc_probs_povm.argtypes = [C.c_int, c_double_p, C.c_int, c_double_p, c_double_p]
         L.orc_loglik.argtypes = [C.c_int, c_int64_p, c_double_p]
         L.orc_loglik.restype = C.c_double
+        L.orc_loglik_poisson.argtypes = [C.c_int, c_int64_p, c_double_p, c_double_p]
+        L.orc_loglik_poisson.restype = C.c_double
         L.orc_mlp_forward.argtypes = [C.POINTER(_Mlp), c_double_p]
         L.orc_mlp_forward.restype = C.c_double
         L.orc_init_chains.argtypes = [C.POINTER(_RunDesc), C.POINTER(_State)]
@@ -234,6 +237,14 @@ def loglik(Q, counts, p):
     return lib().orc_loglik(Q, _p(c, c_int64_p), _p(pp))
 
 
+def loglik_poisson(Q, counts, intensity, p):
+    """Poisson log L = sum_{n>0} n ln p - sum lambda p (see the C file)."""
+    c = np.ascontiguousarray(counts, dtype=np.int64).reshape(-1)
+    lam = np.ascontiguousarray(intensity, dtype=np.float64).reshape(-1)
+    pp = np.ascontiguousarray(p, dtype=np.float64).reshape(-1)
+    return lib().orc_loglik_poisson(Q, _p(c, c_int64_p), _p(lam), _p(pp))
+
+
 def loglik_of_x(Q, counts, x):
     return loglik(Q, counts, probs(Q, rho_of_x(Q, x)))
 
@@ -301,6 +312,7 @@ class RunParams:
     param: str = "gamma"            # "bures": Algorithm 1 (4D^2 parameters)
     povm: np.ndarray | None = None  # [n, D, D] POVM elements (counts then has n entries)
     alpha: float = 0.5              # param "dirichlet": concentration of the weights
+    intensity: np.ndarray | None = None  # Poisson counts with means intensity * p (one per count)
 
 
 class Chains:
@@ -319,6 +331,10 @@ class Chains:
             self._povm = _interleave(params.povm)
             self.counts = np.concatenate([self.counts, np.zeros(self.K * self.D - n, dtype=np.int64)])
         assert self.counts.shape == (self.K * self.D,)
+        self._intensity = None
+        if params.intensity is not None:
+            lam = np.asarray(params.intensity, dtype=np.float64).reshape(-1)
+            self._intensity = np.ascontiguousarray(np.concatenate([lam, np.zeros(self.K * self.D - lam.size)]))
         self.p = params
         R, D2 = params.n_chains, self.D * self.D
         self.x = np.zeros((R, self.d))
@@ -342,7 +358,7 @@ class Chains:
                         p.adapt_lo, p.adapt_hi, p.adapt_factor, p.adapt_until, p.seed,
                         self._mlp, p.trace_chains, p.record_every, p.record_chains,
                         PARAMS[p.param], _p(self._povm),
-                        0 if p.povm is None else int(p.povm.shape[0]), float(p.alpha))
+                        0 if p.povm is None else int(p.povm.shape[0]), float(p.alpha), _p(self._intensity))
 
     def _state(self, n_steps, bufs):
         R = self.p.n_chains

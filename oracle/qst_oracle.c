@@ -478,6 +478,29 @@ double orc_loglik(int Q, const int64_t* counts, const double* p)
     return ll;
 }
 
+/* Poisson counts, a likelihood other than the multinomial one (Section
+ * "Proposed Approach": other likelihoods change only the likelihood steps of
+ * Algorithm 2): the count of projector m is Poisson with mean lambda_m p_m,
+ * independently of the others, with known intensities lambda_m >= 0 (shots
+ * of the setting times the efficiency of the outcome's detector, say).  Up to
+ * the constant sum_m (n_m ln lambda_m - ln n_m!),
+ *   log L = sum_{n_m > 0} n_m ln p_m - sum_m lambda_m p_m,
+ * the second sum over every projector; -inf if a p <= 0 carries a count. */
+double orc_loglik_poisson(int Q, const int64_t* counts, const double* lambda, const double* p)
+{
+    const int D = 1 << Q;
+    int K = 1;
+    for (int q = 0; q < Q; ++q) K *= 3;
+    double ll = 0.0, lin = 0.0;
+    for (int m = 0; m < K * D; ++m) {
+        lin += lambda[m] * p[m];
+        if (counts[m] == 0) continue;
+        if (!(p[m] > 0.0)) return -INFINITY;
+        ll += (double)counts[m] * log(p[m]);
+    }
+    return ll - lin;
+}
+
 /* ----------------------------------------------------------------------- */
 /* MLP surrogate s(x) for delayed acceptance, FP64:                          */
 /* h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2), s = out_scale*(w3.h2 + b3)   */
@@ -537,6 +560,7 @@ typedef struct {
     const double* povm;         /* NULL: the Pauli settings; else n_povm POVM elements (counts padded) */
     int32_t n_povm;
     double alpha;               /* param 2: Dirichlet concentration of the weights */
+    const double* intensity;    /* NULL: multinomial counts; else Poisson means lambda_m p_m (K*D, padded) */
 } orc_run_desc;
 
 /* Per-chain state; arrays are indexed by local chain index r in [0, n_chains). */
@@ -574,7 +598,7 @@ static double eval_state(const orc_run_desc* rd, const double* x, double* rho, d
     orc_pack(Q, rho, packed);
     if (rd->povm) orc_probs_povm(Q, rho, rd->n_povm, rd->povm, p);
     else orc_probs(Q, rho, p);
-    return orc_loglik(Q, rd->counts, p);
+    return rd->intensity ? orc_loglik_poisson(Q, rd->counts, rd->intensity, p) : orc_loglik(Q, rd->counts, p);
 }
 
 /* Initialise chains: Algorithm 2, line 1 (y^0 ~ N(0,I) from step 0's normals). */

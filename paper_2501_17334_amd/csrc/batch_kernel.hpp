@@ -58,6 +58,23 @@ constexpr size_t batch_lds_doubles()
            WgTables<Q>::kDoubles;
 }
 
+// What a tile touches fits what its launch is given: chain_tile addresses
+// the workgroup tables [0, WgTables::kDoubles) and WG / G team regions of
+// kLdsChain doubles after them, and the host passes batch_lds_doubles<Q>()
+// for the class of Q; the workgroup holds whole teams, and the total stays
+// within the 160 KB of LDS of a gfx950 CU.
+template <int Q>
+constexpr bool batch_layout_ok()
+{
+    constexpr int WG = batch_wg(batch_class(Q)), G = BatchTeam<Q>::G;
+    return WG % G == 0 && batch_lds_doubles<Q>() * sizeof(double) <= 160 * 1024 &&
+           batch_lds_doubles<Q>() ==
+               WgTables<Q>::kDoubles + static_cast<size_t>(WG / G) * TeamShape<Q, G>::kLdsChain;
+}
+static_assert(batch_layout_ok<1>() && batch_layout_ok<2>() && batch_layout_ok<3>() && batch_layout_ok<4>() &&
+                  batch_layout_ok<5>() && batch_layout_ok<6>(),
+              "batch tile LDS layout");
+
 // One tile of qubit count Q, inlined into the launch of its class as the
 // single-problem kernel inlines its chain step.  (One launch for all qubit
 // counts, with each count's tile as a callee of its own, needed long

@@ -83,6 +83,7 @@ struct ChainArgs {
     int32_t thin;
     int32_t adapt_every;
     int32_t init;           // 1: draw y^0 (step 0) and evaluate it first
+    int32_t poisson;        // 1: Poisson counts: log L -= sum_p W[p] rho_p, W = nd + KD (packed)
     double beta0;
     double adapt_lo, adapt_hi, adapt_factor;
     uint64_t seed;
@@ -254,6 +255,19 @@ __device__ __forceinline__ double team_loglik(double part_e, double part_f, int 
 {
     const double part = bad ? -INFINITY : __builtin_fma(part_e, kLn2, part_f);
     return team_sum<G>(part, scratch, lane);
+}
+
+// The linear part of the Poisson log-likelihood, sum_m lambda_m p_m =
+// Tr(rho Lambda) with Lambda = sum_m lambda_m Pi_m, as the dot product of
+// packed rho with the packed weights W of Lambda (W[a][a] = Lambda_aa,
+// W[a][b] = 2 Re Lambda_ab and W[b][a] = 2 Im Lambda_ab for a < b): this
+// lane's share, p = lane, lane + G, ...
+template <int Q, int G>
+__device__ __forceinline__ double linear_share(const double* __restrict__ W, const double* rhoP, int lane)
+{
+    double s = 0.0;
+    for (int p = lane; p < Dims<Q>::D2; p += G) s = __builtin_fma(W[p], rhoP[p], s);
+    return s;
 }
 
 // Synchronisation of one team's LDS traffic.  A team of at most 64 lanes
@@ -1188,6 +1202,7 @@ __device__ __forceinline__ void dense_partials(const double* lds_teams, int off_
 #pragma unroll 1
     for (int nt = wave; nt < DS::NT; nt += NWAVES) {
         double pr[4];
+        float pr32[4];
         if constexpr (PREC == kPrecF64) {
             const double* A = static_cast<const double*>(mfrag) + static_cast<size_t>(nt) * DS::KS4 * 64;
             const double* B = team_base + off_rho;
@@ -1205,7 +1220,7 @@ __device__ __forceinline__ void dense_partials(const double* lds_teams, int off_
             for (int ks = 0; ks < DS::KS4; ++ks)
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks * 64 + l], B[4 * ks + kq], acc, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) pr[r] = static_cast<double>(acc[r]);
+            for (int r = 0; r < 4; ++r) pr32[r] = acc[r];
         } else {
             const dense_bf16x8* A = static_cast<const dense_bf16x8*>(mfrag) + static_cast<size_t>(nt) * DS::KS32 * 64;
             const __bf16* B = reinterpret_cast<const __bf16*>(team_base + off_stage);
@@ -1221,23 +1236,29 @@ __device__ __forceinline__ void dense_partials(const double* lds_teams, int off_
                 }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) pr[r] = static_cast<double>(acc[r]);
+            for (int r = 0; r < 4; ++r) pr32[r] = acc[r];
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = PREC == kPrecF64 ? kq + 4 * r : 4 * kq + r;
             const int kl = 16 * nt + row;
             const double n = kl < DS::KD ? nd[kl] : 0.0;
-            double p = pr[r];
-            // reduced precision: a probability that rounds below the smallest
-            // normal FP32 value is taken at that value
-            if constexpr (PREC != kPrecF64) p = fmax(p, 0x1.0p-126);
-            const bool pos = p > 0.0;
-            bad |= (n > 0.0 && !pos) ? 1 : 0;
-            int ex;
-            const double fr = log_parts(pos ? p : 1.0, logtab, ex);
-            part_e = __builtin_fma(n, static_cast<double>(ex), part_e);
-            part_f = __builtin_fma(n, fr, part_f);
+            if constexpr (PREC == kPrecF64) {
+                const double p = pr[r];
+                const bool pos = p > 0.0;
+                bad |= (n > 0.0 && !pos) ? 1 : 0;
+                int ex;
+                const double fr = log_parts(pos ? p : 1.0, logtab, ex);
+                part_e = __builtin_fma(n, static_cast<double>(ex), part_e);
+                part_f = __builtin_fma(n, fr, part_f);
+            } else {
+                // reduced precision: log2 p by the hardware FP32 logarithm of
+                // the FP32 probability (one that rounds below the smallest
+                // normal FP32 value taken at that value), summed in FP64 in
+                // units of ln 2 beside the FP64 form's exponents
+                const float p = fmaxf(pr32[r], 0x1.0p-126f);
+                part_e = __builtin_fma(n, static_cast<double>(__builtin_amdgcn_logf(p)), part_e);
+            }
         }
     }
     // fold the four row groups of each column (lanes l, l^16, l^32, l^48)
@@ -1423,23 +1444,27 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             stage_rho<Q, G>(ybuf, ybuf + 2 * D2, wt, rhoP, lane);
         }
         sync();
+        double llv;
         if constexpr (PATH == kPathDense) {
-            return dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, PATH>::kOffRed, A.mfrag, A.nd, logtab, tid);
+            llv = dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, PATH>::kOffRed, A.mfrag, A.nd, logtab, tid);
         } else if constexpr (PREC == kPrecF32) {
             float* pauli32 = reinterpret_cast<float*>(pauli);
             stage_pauli_f32<Q, G>(rhoP, pauli32, lane);
             sync();
             double part = 0.0;
             stage_loglik_f32<Q, G>(pauli32, A.nd, A.mu, A.ndv, A.muv, lane, part);
-            return kLn2 * team_sum<G>(part, misc + 4, lane);
+            llv = kLn2 * team_sum<G>(part, misc + 4, lane);
         } else {
             stage_pauli<Q, G>(rhoP, pauli, lane);
             sync();
             double part_e = 0.0, part_f = 0.0;
             int bad = 0;
             stage_loglik<Q, G>(pauli, A.nd, A.mu, A.ndv, A.muv, tables, lane, part_e, part_f, bad);
-            return team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
+            llv = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
         }
+        if (A.poisson)      // Poisson counts: minus sum_m lambda_m p_m, in FP64 from packed rho
+            llv -= team_sum<G>(linear_share<Q, G>(A.nd + Dm::KD, rhoP, lane), misc + 4, lane);
+        return llv;
     };
 
     // ---- load or initialise the chain state ----
@@ -1619,7 +1644,7 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainA
 template <int Q, int G, int WG, int PREC = kPrecF64>
 __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, const uint16_t* __restrict__ mug,
                                                const double* __restrict__ ndv, const uint16_t* __restrict__ muv,
-                                               const double* rho, int64_t n, double* ll_out)
+                                               const double* rho, int64_t n, double* ll_out, int poisson)
 {
     using Dm = Dims<Q>;
     using S = TeamShape<Q, G>;
@@ -1648,45 +1673,243 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
         __syncthreads();
         double part = 0.0;
         stage_loglik_f32<Q, G>(pauli32, nd, mug, ndv, muv, lane, part);
-        const double tot = team_sum<G>(part, misc + 4, lane);
-        if (live && lane == 0) ll_out[idx] = kLn2 * tot;
+        double ll = kLn2 * team_sum<G>(part, misc + 4, lane);
+        if (poisson) ll -= team_sum<G>(linear_share<Q, G>(nd + Dm::KD, rhoP, lane), misc + 4, lane);
+        if (live && lane == 0) ll_out[idx] = ll;
     } else {
         stage_pauli<Q, G>(rhoP, pauli, lane);
         __syncthreads();
         double part_e = 0.0, part_f = 0.0;
         int bad = 0;
         stage_loglik<Q, G>(pauli, nd, mug, ndv, muv, tables, lane, part_e, part_f, bad);
-        const double ll = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
+        double ll = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
+        if (poisson) ll -= team_sum<G>(linear_share<Q, G>(nd + Dm::KD, rhoP, lane), misc + 4, lane);
         if (live && lane == 0) ll_out[idx] = ll;
     }
 }
 
-// Dense-path Eq. (likelihood) for n given density matrices: 16 matrices per
-// workgroup of 16 waves.
+// ---------------------------------------------------------------------------
+// Eq. (likelihood) for n given density matrices on the dense path, alone
+// (qst_loglik): 64 matrices per 1024-thread workgroup (48 for BF16x3), so
+// that each fragment of M, streamed from L2, feeds four (three) MFMAs, one
+// per 16-column block of matrices, instead of one.  Their B operands sit in
+// LDS in the precision's format, one padded row per matrix; wave w computes
+// the output tiles w, w + 16, ... of all the workgroup's matrices and keeps
+// per-lane sums of c log p for its columns; the 16 waves' sums are added in
+// wave order.  BF16x3 takes 48 matrices so that its three-part operands
+// (76 KB) leave room for a second workgroup per CU, whose HBM reads of rho
+// then overlap the first one's MFMAs.
+// ---------------------------------------------------------------------------
+template <int Q, int PREC>
+struct DenseAloneShape {
+    using DS = DenseShape<Q>;
+    static constexpr int kStates = PREC == kPrecBF16x3 ? 48 : 64;   // matrices per workgroup
+    static constexpr int kBlocks = kStates / 16;       // 16-column MFMA blocks
+    // B row stride in elements of the operand type, padded against LDS bank
+    // conflicts between the 16 rows one MFMA reads
+    static constexpr int kStrideF64 = DS::K + 1;       // doubles
+    static constexpr int kStrideF32 = DS::K + 1;       // floats
+    static constexpr int kStrideBF16 = 3 * DS::KP32 + 8;   // bf16: hi | mid | lo parts
+    static constexpr size_t kOperandBytes =
+        PREC == kPrecF64 ? size_t(kStates) * kStrideF64 * 8
+                         : (PREC == kPrecF32 ? size_t(kStates) * kStrideF32 * 4 : size_t(kStates) * kStrideBF16 * 2);
+    static constexpr size_t kRedBytes = size_t(16) * kStates * 3 * 8;   // [wave][matrix] (e, f, bad)
+    static constexpr size_t kBodyBytes = kOperandBytes > kRedBytes ? kOperandBytes : kRedBytes;
+    static constexpr size_t kLdsBytes = size_t(2 * kLogTableSize) * 8 + (kBodyBytes + 15) / 16 * 16;
+};
+
 template <int Q, int PREC>
 __global__ __launch_bounds__(1024) void k_loglik_dense(const double* __restrict__ nd, const void* mfrag,
-                                                       const double* rho, int64_t n, double* ll_out)
+                                                       const double* rho, int64_t n, double* ll_out, int poisson)
 {
     using Dm = Dims<Q>;
-    using S = TeamShape<Q, 64, kPathDense>;
-    constexpr int D = Dm::D, D2 = Dm::D2;
+    using DS = DenseShape<Q>;
+    using SH = DenseAloneShape<Q, PREC>;
+    constexpr int D = Dm::D, D2 = Dm::D2, NS = SH::kStates;
     extern __shared__ double lds_all[];
-    wg_tables_init<Q, kPathDense>(lds_all, threadIdx.x, 1024);
-    double* tables = lds_all;
-    double* lds = lds_all + WgTables<Q, kPathDense>::kDoubles;
-    const int tid = threadIdx.x, team = tid >> 6, lane = tid & 63;
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 16 + team;
-    const bool live = idx < n;
-    const int64_t c = live ? idx : 0;
-    double* rhoP = lds + team * S::kLds + S::kOffRho;
-    for (int p = lane; p < D2; p += 64) {
-        const int a = p / D, b = p % D;
-        rhoP[p] = a <= b ? rho[(c * D2 + a * D + b) * 2] : rho[(c * D2 + b * D + a) * 2 + 1];
+    const LogEntry* logtab = reinterpret_cast<const LogEntry*>(lds_all);
+    log_table_init(reinterpret_cast<LogEntry*>(lds_all), threadIdx.x, 1024);
+    char* body = reinterpret_cast<char*>(lds_all + 2 * kLogTableSize);
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, col = l & 15, kq = l >> 4;
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * NS;
+
+    // B operands: packed rho (Re rho_ab for a <= b, Im rho_ba for a > b) of
+    // each matrix, zero for matrices past n
+    for (int e = tid; e < NS * DS::KP32; e += 1024) {
+        const int sidx = e / DS::KP32, k = e % DS::KP32;
+        const int64_t idx = first + sidx;
+        double x = 0.0;
+        if (idx < n && k < D2) {
+            const int a = k / D, b = k % D;
+            x = a <= b ? rho[(idx * D2 + a * D + b) * 2] : rho[(idx * D2 + b * D + a) * 2 + 1];
+        }
+        if constexpr (PREC == kPrecF64) {
+            if (k < D2) reinterpret_cast<double*>(body)[sidx * SH::kStrideF64 + k] = x;
+        } else if constexpr (PREC == kPrecF32) {
+            if (k < D2) reinterpret_cast<float*>(body)[sidx * SH::kStrideF32 + k] = static_cast<float>(x);
+        } else {
+            // three BF16 parts, each the rounding of what the previous leave
+            __bf16* h = reinterpret_cast<__bf16*>(body) + sidx * SH::kStrideBF16;
+            const __bf16 hi = static_cast<__bf16>(static_cast<float>(x));
+            const double r1 = x - static_cast<double>(static_cast<float>(hi));
+            const __bf16 mid = static_cast<__bf16>(static_cast<float>(r1));
+            const double r2 = r1 - static_cast<double>(static_cast<float>(mid));
+            h[k] = hi;
+            h[DS::KP32 + k] = mid;
+            h[2 * DS::KP32 + k] = static_cast<__bf16>(static_cast<float>(r2));
+        }
     }
     __syncthreads();
-    const double ll = dense_loglik_wg<Q, PREC>(lds, tables + WgTables<Q, kPathDense>::kOffRed, mfrag, nd,
-                                               reinterpret_cast<const LogEntry*>(tables), tid);
-    if (live && lane == 0) ll_out[idx] = ll;
+
+    double pe[SH::kBlocks], pf[SH::kBlocks];
+    int bad[SH::kBlocks];                             // per column block: a p <= 0 that carries a count
+#pragma unroll
+    for (int cb = 0; cb < SH::kBlocks; ++cb) {
+        pe[cb] = pf[cb] = 0.0;
+        bad[cb] = 0;
+    }
+    // BF16x3 takes two output tiles per pass, so that every B fragment read
+    // from LDS feeds two MFMAs (its LDS traffic, not the MFMA pipe, was the
+    // bound with one)
+    constexpr int TPG = PREC == kPrecBF16x3 ? 2 : 1;
+#pragma unroll 1
+    for (int nt0 = wave; nt0 < DS::NT; nt0 += 16 * TPG) {
+        if constexpr (PREC == kPrecF64) {
+            const int nt = nt0;
+            const double* A = static_cast<const double*>(mfrag) + static_cast<size_t>(nt) * DS::KS4 * 64;
+            const double* B = reinterpret_cast<const double*>(body) + col * SH::kStrideF64 + kq;
+            dense_f64x4 acc[SH::kBlocks];
+#pragma unroll
+            for (int cb = 0; cb < SH::kBlocks; ++cb) acc[cb] = dense_f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int ks = 0; ks < DS::KS4; ++ks) {
+                const double a = A[ks * 64 + l];
+#pragma unroll
+                for (int cb = 0; cb < SH::kBlocks; ++cb)
+                    acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[16 * cb * SH::kStrideF64 + 4 * ks], acc[cb],
+                                                                   0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int kl = 16 * nt + kq + 4 * r;          // FP64 result register r: row l/16 + 4r
+                const double c = kl < DS::KD ? nd[kl] : 0.0;
+#pragma unroll
+                for (int cb = 0; cb < SH::kBlocks; ++cb) {
+                    const double p = acc[cb][r];
+                    const bool pos = p > 0.0;
+                    bad[cb] |= (c > 0.0 && !pos) ? 1 : 0;
+                    int ex;
+                    const double fr = log_parts(pos ? p : 1.0, logtab, ex);
+                    pe[cb] = __builtin_fma(c, static_cast<double>(ex), pe[cb]);
+                    pf[cb] = __builtin_fma(c, fr, pf[cb]);
+                }
+            }
+        } else {
+            dense_f32x4 acc[TPG][SH::kBlocks];
+#pragma unroll
+            for (int t = 0; t < TPG; ++t)
+#pragma unroll
+                for (int cb = 0; cb < SH::kBlocks; ++cb) acc[t][cb] = dense_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            if constexpr (PREC == kPrecF32) {
+                const float* A = static_cast<const float*>(mfrag) + static_cast<size_t>(nt0) * DS::KS4 * 64;
+                const float* B = reinterpret_cast<const float*>(body) + col * SH::kStrideF32 + kq;
+#pragma unroll 4
+                for (int ks = 0; ks < DS::KS4; ++ks) {
+                    const float a = A[ks * 64 + l];
+#pragma unroll
+                    for (int cb = 0; cb < SH::kBlocks; ++cb)
+                        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, B[16 * cb * SH::kStrideF32 + 4 * ks],
+                                                                          acc[0][cb], 0, 0, 0);
+                }
+            } else {
+                const bool second = nt0 + 16 < DS::NT;        // the pass's second tile exists (wave-uniform)
+                const dense_bf16x8* A0 =
+                    static_cast<const dense_bf16x8*>(mfrag) + static_cast<size_t>(nt0) * DS::KS32 * 64;
+                const dense_bf16x8* A1 = A0 + static_cast<size_t>(16) * DS::KS32 * 64;
+                const __bf16* B = reinterpret_cast<const __bf16*>(body) + col * SH::kStrideBF16 + 8 * kq;
+                // one k-step at a time: its B fragments already fill 36 registers
+#pragma unroll 1
+                for (int ks = 0; ks < DS::KS32; ++ks) {
+                    const dense_bf16x8 a0 = A0[ks * 64 + l];
+                    const dense_bf16x8 a1 = second ? A1[ks * 64 + l] : a0;
+#pragma unroll
+                    for (int cb = 0; cb < SH::kBlocks; ++cb)
+#pragma unroll
+                        for (int part = 0; part < 3; ++part) {
+                            const dense_bf16x8 b = *reinterpret_cast<const dense_bf16x8*>(
+                                B + 16 * cb * SH::kStrideBF16 + part * DS::KP32 + 32 * ks);
+                            acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][cb], 0, 0, 0);
+                            if (second)
+                                acc[TPG - 1][cb] =
+                                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[TPG - 1][cb], 0, 0, 0);
+                        }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < TPG; ++t) {
+                const int nt = nt0 + 16 * t;
+                if (nt >= DS::NT) break;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int kl = 16 * nt + 4 * kq + r;      // FP32 result register r: row 4 (l/16) + r
+                    const double c = kl < DS::KD ? nd[kl] : 0.0;
+#pragma unroll
+                    for (int cb = 0; cb < SH::kBlocks; ++cb) {
+                        // log2 p by the hardware FP32 logarithm (p clamped at the
+                        // smallest normal FP32 value), summed in FP64
+                        const float p = fmaxf(acc[t][cb][r], 0x1.0p-126f);
+                        pe[cb] = __builtin_fma(c, static_cast<double>(__builtin_amdgcn_logf(p)), pe[cb]);
+                    }
+                }
+            }
+        }
+    }
+    // fold the four row groups of each column (lanes l, l^16, l^32, l^48)
+#pragma unroll
+    for (int cb = 0; cb < SH::kBlocks; ++cb) {
+        pe[cb] += __shfl_xor(pe[cb], 16, 64);
+        pf[cb] += __shfl_xor(pf[cb], 16, 64);
+        pe[cb] += __shfl_xor(pe[cb], 32, 64);
+        pf[cb] += __shfl_xor(pf[cb], 32, 64);
+        bad[cb] |= __shfl_xor(bad[cb], 16, 64);
+        bad[cb] |= __shfl_xor(bad[cb], 32, 64);
+    }
+    __syncthreads();                                  // the operand region becomes the reduction area
+    double* red = reinterpret_cast<double*>(body);
+    if (l < 16) {
+#pragma unroll
+        for (int cb = 0; cb < SH::kBlocks; ++cb) {
+            double* o = red + (static_cast<size_t>(wave) * NS + 16 * cb + col) * 3;
+            o[0] = pe[cb];
+            o[1] = pf[cb];
+            o[2] = static_cast<double>(bad[cb]);
+        }
+    }
+    __syncthreads();
+    if (tid < NS && first + tid < n) {
+        double te = 0.0, tf = 0.0;
+        int tb = 0;
+        for (int w = 0; w < 16; ++w) {
+            const double* o = red + (static_cast<size_t>(w) * NS + tid) * 3;
+            te += o[0];
+            tf += o[1];
+            tb |= static_cast<int>(o[2]);
+        }
+        double ll = tb ? -INFINITY : __builtin_fma(te, kLn2, tf);
+        if (poisson) {
+            // minus sum_m lambda_m p_m = Tr(rho Lambda), packed weights after the counts
+            const double* W = nd + Dm::KD;
+            const int64_t idx = first + tid;
+            double lin = 0.0;
+            for (int k = 0; k < D2; ++k) {
+                const int a = k / D, b = k % D;
+                const double x = a <= b ? rho[(idx * D2 + a * D + b) * 2] : rho[(idx * D2 + b * D + a) * 2 + 1];
+                lin = __builtin_fma(W[k], x, lin);
+            }
+            ll -= lin;
+        }
+        ll_out[first + tid] = ll;
+    }
 }
 
 }  // namespace qst

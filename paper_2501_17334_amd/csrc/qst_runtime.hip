@@ -207,6 +207,57 @@ std::vector<double> povm_matrix_packed(int Q, const double* povm, int n)
     return M;
 }
 
+// Packed weights of Lambda = sum_m lambda_m Pi_m for the linear part of the
+// Poisson log-likelihood (sum_m lambda_m p_m = Tr(rho Lambda)): W[a][a] =
+// Lambda_aa, W[a][b] = 2 Re Lambda_ab and W[b][a] = 2 Im Lambda_ab for a < b,
+// so that Tr(rho Lambda) = sum_k W[k] (packed rho)[k].  Pauli settings:
+// Lambda accumulated from the product eigenvectors e_kl (Pi_kl = e e^dag);
+// user POVM elements: the rows of their packed matrix M weighted by lambda.
+std::vector<double> linear_weights_packed(int Q, const double* lambda, int n, const std::vector<double>& povm_M)
+{
+    const int D = 1 << Q, D2 = D * D, K = ipow3(Q);
+    std::vector<double> W(D2, 0.0);
+    if (!povm_M.empty()) {
+        for (int m = 0; m < n; ++m)
+            for (int k = 0; k < D2; ++k) W[k] += lambda[m] * povm_M[static_cast<size_t>(m) * D2 + k];
+        return W;
+    }
+    // one qubit's eigenvectors: X (1, +-1)/sqrt 2, Y (1, +-i)/sqrt 2, Z e_0 / e_1
+    auto comp = [](int s, int b, int x) -> std::complex<double> {
+        const double r = 0.70710678118654752440;
+        const double sgn = b == 0 ? 1.0 : -1.0;
+        if (s == 2) return x == b ? 1.0 : 0.0;
+        if (x == 0) return r;
+        return s == 0 ? std::complex<double>(sgn * r, 0.0) : std::complex<double>(0.0, sgn * r);
+    };
+    std::vector<std::complex<double>> L(static_cast<size_t>(D2), 0.0), e(D);
+    for (int k = 0; k < K; ++k) {
+        int dig[8];
+        for (int q = Q - 1, kk = k; q >= 0; --q) { dig[q] = kk % 3; kk /= 3; }
+        for (int l = 0; l < D; ++l) {
+            const double lam = lambda[k * D + l];
+            if (lam == 0.0) continue;
+            for (int a = 0; a < D; ++a) {
+                std::complex<double> v = 1.0;
+                for (int q = 0; q < Q; ++q) v *= comp(dig[q], (l >> (Q - 1 - q)) & 1, (a >> (Q - 1 - q)) & 1);
+                e[a] = v;
+            }
+            for (int a = 0; a < D; ++a)
+                for (int b = a; b < D; ++b) L[static_cast<size_t>(a) * D + b] += lam * e[a] * std::conj(e[b]);
+        }
+    }
+    for (int a = 0; a < D; ++a)
+        for (int b = a; b < D; ++b) {
+            const std::complex<double> v = L[static_cast<size_t>(a) * D + b];
+            if (a == b) W[a * D + a] = v.real();
+            else {
+                W[a * D + b] = 2.0 * v.real();
+                W[b * D + a] = 2.0 * v.imag();
+            }
+        }
+    return W;
+}
+
 // The measurement matrix in the dense kernels' MFMA operand order.
 std::vector<uint8_t> matrix_fragments(int Q, const std::vector<double>& M, int prec)
 {
@@ -292,20 +343,21 @@ void launch_chains_t(const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
 
 template <int Q, int PREC>
 void launch_loglik_dense_t(const double* nd, const void* mfrag, const double* rho, int64_t n, double* out,
-                           hipStream_t s)
+                           int poisson, hipStream_t s)
 {
-    using S = qst::TeamShape<Q, 64, qst::kPathDense>;
-    const int64_t blocks = (n + 15) / 16;
-    const size_t lds = (16 * static_cast<size_t>(S::kLds) + qst::WgTables<Q, qst::kPathDense>::kDoubles) * sizeof(double);
+    using SH = qst::DenseAloneShape<Q, PREC>;
+    const int64_t blocks = (n + SH::kStates - 1) / SH::kStates;
+    if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many matrices for one launch");
+    const size_t lds = SH::kLdsBytes;
     allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_loglik_dense<Q, PREC>), lds);
     hipLaunchKernelGGL((qst::k_loglik_dense<Q, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(1024), lds, s, nd,
-                       mfrag, rho, n, out);
+                       mfrag, rho, n, out, poisson);
     hip_check(hipGetLastError(), "dense loglik kernel launch");
 }
 
 template <int Q, int G, int WG, int PREC>
 void launch_loglik_t(const double* nd, const uint16_t* mu, const double* ndv, const uint16_t* muv, const double* rho,
-                     int64_t n, double* out, hipStream_t s)
+                     int64_t n, double* out, int poisson, hipStream_t s)
 {
     using S = qst::TeamShape<Q, G>;
     const int64_t teams = WG / G;
@@ -314,7 +366,7 @@ void launch_loglik_t(const double* nd, const uint16_t* mu, const double* ndv, co
     allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_loglik<Q, G, WG, PREC>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many states for one launch");
     hipLaunchKernelGGL((qst::k_loglik<Q, G, WG, PREC>), dim3(static_cast<unsigned>(blocks)), dim3(WG), lds, s, nd,
-                       mu, ndv, muv, rho, n, out);
+                       mu, ndv, muv, rho, n, out, poisson);
     hip_check(hipGetLastError(), "loglik kernel launch");
 }
 
@@ -375,11 +427,11 @@ void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a,
 }
 
 void launch_loglik_dense(int Q, int prec, const double* nd, const void* mfrag, const double* rho, int64_t n,
-                         double* out, hipStream_t s)
+                         double* out, int poisson, hipStream_t s)
 {
     using namespace qst;
 #define QST_DENSE(q, pr) \
-    if (Q == q && prec == pr) return launch_loglik_dense_t<q, pr>(nd, mfrag, rho, n, out, s);
+    if (Q == q && prec == pr) return launch_loglik_dense_t<q, pr>(nd, mfrag, rho, n, out, poisson, s);
     QST_DENSE(1, kPrecF64) QST_DENSE(1, kPrecF32) QST_DENSE(1, kPrecBF16x3)
     QST_DENSE(2, kPrecF64) QST_DENSE(2, kPrecF32) QST_DENSE(2, kPrecBF16x3)
     QST_DENSE(3, kPrecF64) QST_DENSE(3, kPrecF32) QST_DENSE(3, kPrecBF16x3)
@@ -390,26 +442,24 @@ void launch_loglik_dense(int Q, int prec, const double* nd, const void* mfrag, c
 
 template <int PREC>
 void launch_loglik_p(int Q, const double* nd, const uint16_t* mu, const double* ndv, const uint16_t* muv,
-                     const double* rho, int64_t n, double* out,
-                     hipStream_t s)
+                     const double* rho, int64_t n, double* out, int poisson, hipStream_t s)
 {
     switch (Q) {
-        case 1: return launch_loglik_t<1, 8, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
-        case 2: return launch_loglik_t<2, 16, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
-        case 3: return launch_loglik_t<3, 32, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
-        case 4: return launch_loglik_t<4, 64, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
-        case 5: return launch_loglik_t<5, 64, 64, PREC>(nd, mu, ndv, muv, rho, n, out, s);
-        case 6: return launch_loglik_t<6, 256, 256, PREC>(nd, mu, ndv, muv, rho, n, out, s);
+        case 1: return launch_loglik_t<1, 8, 64, PREC>(nd, mu, ndv, muv, rho, n, out, poisson, s);
+        case 2: return launch_loglik_t<2, 16, 64, PREC>(nd, mu, ndv, muv, rho, n, out, poisson, s);
+        case 3: return launch_loglik_t<3, 32, 64, PREC>(nd, mu, ndv, muv, rho, n, out, poisson, s);
+        case 4: return launch_loglik_t<4, 64, 64, PREC>(nd, mu, ndv, muv, rho, n, out, poisson, s);
+        case 5: return launch_loglik_t<5, 64, 64, PREC>(nd, mu, ndv, muv, rho, n, out, poisson, s);
+        case 6: return launch_loglik_t<6, 256, 256, PREC>(nd, mu, ndv, muv, rho, n, out, poisson, s);
     }
     fail(QST_ERR_INVALID, "bad Q");
 }
 
 void launch_loglik(int Q, int prec, const double* nd, const uint16_t* mu, const double* ndv, const uint16_t* muv,
-                   const double* rho, int64_t n, double* out,
-                   hipStream_t s)
+                   const double* rho, int64_t n, double* out, int poisson, hipStream_t s)
 {
-    if (prec == qst::kPrecF32) return launch_loglik_p<qst::kPrecF32>(Q, nd, mu, ndv, muv, rho, n, out, s);
-    return launch_loglik_p<qst::kPrecF64>(Q, nd, mu, ndv, muv, rho, n, out, s);
+    if (prec == qst::kPrecF32) return launch_loglik_p<qst::kPrecF32>(Q, nd, mu, ndv, muv, rho, n, out, poisson, s);
+    return launch_loglik_p<qst::kPrecF64>(Q, nd, mu, ndv, muv, rho, n, out, poisson, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,7 +510,8 @@ struct qst_problem {
     double alpha = 0.5;           // QST_PARAM_DIRICHLET: concentration of the weights
     std::vector<int64_t> counts;
     std::vector<double> povm_M;   // user POVM: packed measurement matrix (empty: the Pauli settings)
-    double* nd = nullptr;  // counts as doubles
+    bool poisson = false;  // Poisson counts with known intensities (else multinomial)
+    double* nd = nullptr;  // counts as doubles [KD]; with Poisson counts followed by the packed weights W [D2]
     uint16_t* mu = nullptr;  // Pauli index of every (setting, transform position), [KD]
     double* ndv = nullptr;   // counts in the task-major order of the likelihood transforms, [KD]
     uint16_t* muv = nullptr; // Pauli indices in the same order, [KD]
@@ -582,6 +633,8 @@ void validate_run(const qst_problem* p, const qst_run_desc& r)
     if (r.pair_every > 0 && r.surrogate) fail(QST_ERR_UNSUPPORTED, "the pair recorder runs with plain pCN");
     if (r.surrogate && p->param != QST_PARAM_GAMMA)
         fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs with the Gaussian/gamma parameterisation");
+    if (r.surrogate && p->poisson)
+        fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs with the multinomial likelihood");
     // extents of what the kernels write into the caller's buffers
     const size_t steps = static_cast<size_t>(r.n_steps);
     const size_t tc = static_cast<size_t>(std::min<int64_t>(r.trace_chains, r.n_chains));
@@ -688,10 +741,23 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
             if (p->counts[i] < 0) fail(QST_ERR_INVALID, "negative count");
             nd[i] = static_cast<double>(p->counts[i]);
         }
+        std::vector<double> weights;
+        if (desc->intensity) {
+            const int n_int = desc->povm ? desc->n_povm : p->KD;
+            for (int i = 0; i < n_int; ++i)
+                if (!(desc->intensity[i] >= 0.0) || !std::isfinite(desc->intensity[i]))
+                    fail(QST_ERR_INVALID, "intensities must be finite and >= 0");
+            weights = linear_weights_packed(Q, desc->intensity, n_int, p->povm_M);
+            p->poisson = true;
+        }
         DeviceGuard g(p->device);
         (void)scratch_address(p->device);   // set-up of the allocation-free pooling call
-        p->nd = dev_alloc<double>(p->KD);
+        const size_t nd_len = static_cast<size_t>(p->KD) + weights.size();
+        p->nd = dev_alloc<double>(nd_len);
         hip_check(hipMemcpy(p->nd, nd.data(), sizeof(double) * p->KD, hipMemcpyHostToDevice), "copy counts");
+        if (!weights.empty())
+            hip_check(hipMemcpy(p->nd + p->KD, weights.data(), sizeof(double) * weights.size(), hipMemcpyHostToDevice),
+                      "copy Poisson weights");
         // mu(k, t) = sum_q [t_q] (s_q(k) + 1) 4^(Q-1-q): the Pauli string whose
         // coefficient enters position t of setting k's Walsh-Hadamard transform
         std::vector<uint16_t> mu(p->KD);
@@ -810,6 +876,7 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r, bool problem_wid
     a.thin = r.thin;
     a.adapt_every = r.adapt_every;
     a.init = r.resume ? 0 : 1;
+    a.poisson = p->poisson ? 1 : 0;
     a.beta0 = r.beta0;
     a.adapt_lo = r.adapt_lo;
     a.adapt_hi = r.adapt_hi;
@@ -908,9 +975,27 @@ double chain_step_cost(int Q)
     return c[Q];
 }
 
+// Worker streams of the uneven batch, per device: created once at the
+// default priority and kept for the process, so that the launch classes of a
+// batch run side by side instead of back to back.
+constexpr int kBatchStreams = 4;
+
+hipStream_t* batch_streams(int dev)
+{
+    static std::mutex mu;
+    static std::map<int, std::vector<hipStream_t>> streams;
+    std::lock_guard<std::mutex> lock(mu);
+    std::vector<hipStream_t>& v = streams[dev];
+    while (v.size() < static_cast<size_t>(kBatchStreams)) {
+        hipStream_t st = nullptr;
+        hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "batch stream");
+        v.push_back(st);
+    }
+    return v.data();
+}
+
 // One persistent launch per qubit count and precision over its part of the
-// tile list (n tiles from `items`, largest first) with its own counter.  The
-// launches of a batch are queued back to back on the stream.
+// tile list (n tiles from `items`, largest first) with its own counter.
 template <int QMAX, int PREC>
 void launch_batch_class(const qst::BatchItem* items, size_t n, size_t lds, const qst::ChainArgs* dargs,
                         int32_t* counter, int n_cu, hipStream_t s)
@@ -938,7 +1023,9 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
     for (int i = 0; i < n; ++i) {
         qst_problem* p = problems[i];
         if (p->path != QST_PATH_KRON)
-            fail(QST_ERR_UNSUPPORTED, "batched launches use the Kronecker path (FP64 or FP32)");
+            fail(QST_ERR_UNSUPPORTED,
+                 "batched launches use the Kronecker path (FP64 or FP32): the dense forms run only to 4 qubits, "
+                 "each at a fraction of the Kronecker route's rate, and need 16-chain workgroups of their own");
         args[i] = make_args(p, runs[i]);
         const int per = qst::batch_wg(qst::batch_class(p->Q)) / batch_team(p->Q);
         const int32_t prec = p->precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64;
@@ -984,14 +1071,33 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
         hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
         hipLaunchKernelGGL(qst::k_zero_counters, dim3(1), dim3(64), 0, s, counters, kClasses);
         hip_check(hipGetLastError(), "counter reset");
+        // the classes go round-robin onto the worker streams, largest qubit
+        // count first, each stream starting after the work already on s;
+        // whatever CUs a class leaves idle while it drains, the next class
+        // on another stream fills
+        hipStream_t* ws = batch_streams(dev);
+        hipEvent_t start = nullptr, done[kBatchStreams] = {};
+        hip_check(hipEventCreateWithFlags(&start, hipEventDisableTiming), "batch event");
+        for (auto& e : done) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "batch event");
+        hip_check(hipEventRecord(start, s), "batch event record");
+        for (int i = 0; i < kBatchStreams; ++i) hip_check(hipStreamWaitEvent(ws[i], start, 0), "batch stream wait");
+        int next = 0;
+        bool used[kBatchStreams] = {};
         constexpr int F64 = qst::kPrecF64, F32 = qst::kPrecF32;
         auto both = [&](auto qc) {
             constexpr int Q = decltype(qc)::value;
             const int k64 = slot(Q, F64), k32 = slot(Q, F32);
-            launch_batch_class<Q, F64>(ditems + off[k64], off[k64 + 1] - off[k64], lds_class[Q], dargs,
-                                       counters + k64, n_cu, s);
-            launch_batch_class<Q, F32>(ditems + off[k32], off[k32 + 1] - off[k32], lds_class[Q], dargs,
-                                       counters + k32, n_cu, s);
+            for (int k : {k64, k32}) {
+                if (off[k + 1] == off[k]) continue;
+                const int si = next++ % kBatchStreams;
+                used[si] = true;
+                if (k == k64)
+                    launch_batch_class<Q, F64>(ditems + off[k], off[k + 1] - off[k], lds_class[Q], dargs,
+                                               counters + k, n_cu, ws[si]);
+                else
+                    launch_batch_class<Q, F32>(ditems + off[k], off[k + 1] - off[k], lds_class[Q], dargs,
+                                               counters + k, n_cu, ws[si]);
+            }
         };
         both(std::integral_constant<int, 6>{});
         both(std::integral_constant<int, 5>{});
@@ -999,9 +1105,16 @@ void launch_batch(qst_problem* const* problems, int32_t n, const qst_run_desc* r
         both(std::integral_constant<int, 3>{});
         both(std::integral_constant<int, 2>{});
         both(std::integral_constant<int, 1>{});
+        for (int i = 0; i < kBatchStreams; ++i) {
+            if (!used[i]) continue;
+            hip_check(hipEventRecord(done[i], ws[i]), "batch event record");
+            hip_check(hipStreamWaitEvent(s, done[i], 0), "batch join");
+        }
         hip_check(hipStreamSynchronize(s), "batch synchronize");
+        (void)hipEventDestroy(start);
+        for (auto& e : done) (void)hipEventDestroy(e);
     } catch (...) {
-        (void)hipStreamSynchronize(s);   // no launch may still read the buffers freed below
+        (void)hipDeviceSynchronize();    // no launch, on s or a worker stream, may still read the buffers freed below
         dev_free(dargs);
         dev_free(ditems);
         dev_free(counters);
@@ -1048,7 +1161,10 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
                               static_cast<int>(p->precision), a, p->chain0, s);
         } else {
             for (int i = 0; i < n_problems; ++i)
-                if (runs[i].surrogate) fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs one problem per call");
+                if (runs[i].surrogate)
+                    fail(QST_ERR_UNSUPPORTED, "delayed acceptance runs one problem per call: each of its steps is "
+                                              "four launches (propose, network, screen, exact stage) with the "
+                                              "chain state in HBM, not a persistent tile");
             launch_batch(problems, n_problems, runs, s);
         }
         for (int i = 0; i < n_problems; ++i) {
@@ -1244,10 +1360,11 @@ qst_status qst_loglik(const qst_problem* p, const double* rho, int64_t n, double
         DeviceGuard g(p->device);
         if (pth == QST_PATH_DENSE) {
             const void* f = const_cast<qst_problem*>(p)->fragments(precision);
-            launch_loglik_dense(p->Q, precision, p->nd, f, rho, n, ll_out, static_cast<hipStream_t>(stream));
+            launch_loglik_dense(p->Q, precision, p->nd, f, rho, n, ll_out, p->poisson ? 1 : 0,
+                                static_cast<hipStream_t>(stream));
         } else {
             launch_loglik(p->Q, precision == QST_FP32 ? qst::kPrecF32 : qst::kPrecF64, p->nd, p->mu, p->ndv, p->muv,
-                          rho, n, ll_out, static_cast<hipStream_t>(stream));
+                          rho, n, ll_out, p->poisson ? 1 : 0, static_cast<hipStream_t>(stream));
         }
     });
 }

@@ -33,7 +33,8 @@ class QstError(RuntimeError):
 class _ProblemDesc(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("counts", C.POINTER(C.c_int64)),
                 ("precision", C.c_int), ("path", C.c_int), ("device", C.c_int32), ("param", C.c_int),
-                ("povm", C.POINTER(C.c_double)), ("n_povm", C.c_int32), ("alpha", C.c_double)]
+                ("povm", C.POINTER(C.c_double)), ("n_povm", C.c_int32), ("alpha", C.c_double),
+                ("intensity", C.POINTER(C.c_double))]
 
 
 # parameterisation of rho(x): the Gaussian/gamma form (2D^2+D parameters) or
@@ -219,11 +220,12 @@ class Problem:
     """A tomography problem on one GPU (qst_init_problem / qst_free_problem)."""
 
     def __init__(self, n_qubits, counts, precision="fp64", path="auto", device=0, param="gamma", povm=None,
-                 alpha=0.5):
+                 alpha=0.5, intensity=None):
         """param: "gamma" (default), "bures" (Algorithm 1) or "dirichlet"
         (Dirichlet(alpha) weights); povm: optional [n, D, D] complex POVM
         elements in place of the Pauli settings (counts then has n entries;
-        dense path, FP64 or FP32)."""
+        dense path, FP64 or FP32); intensity: optional Poisson intensities,
+        one per count (count m ~ Poisson(intensity_m p_m))."""
         self.Q = int(n_qubits)
         self.D = 2 ** self.Q
         self.K = 3 ** self.Q
@@ -240,9 +242,15 @@ class Problem:
             self._povm = np.ascontiguousarray(np.stack([povm.real, povm.imag], axis=-1))
         elif self.counts.size != self.K * self.D:
             raise ValueError("counts must have 3^Q * 2^Q entries")
+        self._intensity = None
+        if intensity is not None:
+            self._intensity = np.ascontiguousarray(intensity, dtype=np.float64).reshape(-1)
+            if self._intensity.size != self.counts.size:
+                raise ValueError("intensity must have one entry per count")
         desc = _ProblemDesc(self.Q, self.counts.ctypes.data_as(C.POINTER(C.c_int64)),
                             _PREC[precision], _PATH[path], device, _PARAM[param],
-                            _f64(self._povm) if self._povm is not None else None, n_povm, float(alpha))
+                            _f64(self._povm) if self._povm is not None else None, n_povm, float(alpha),
+                            _f64(self._intensity) if self._intensity is not None else None)
         h = C.c_void_p()
         _check(lib().qst_init_problem(C.byref(desc), C.byref(h)))
         self._h = h

@@ -150,6 +150,38 @@ def random_bases_problem(Q, shots=1024, n_bases=None, white=0.1, index=0) -> Pov
     return PovmProblem(f"bases_{Q}", Q, povm, counts, st, CHAIN_SEED + 200 + Q)
 
 
+@dataclass
+class PoissonProblem:
+    """Pauli-setting counts that are independent Poisson variables with known
+    intensities: count (k, l) has mean intensity[k, l] * p_kl."""
+    name: str
+    n_qubits: int
+    counts: np.ndarray          # (3^Q, 2^Q) int64
+    intensity: np.ndarray       # (3^Q, 2^Q) float64
+    truth: TruthState
+    seed: int
+
+
+def poisson_problem(Q, shots=1000, efficiency=(0.9, 0.6), white=0.1, index=0) -> PoissonProblem:
+    """Every Pauli setting runs for `shots` trials, and the detector of each
+    qubit registers outcome b with efficiency efficiency[b]: count (k, l) is
+    Poisson with mean shots * prod_q efficiency[b_q(l)] * p_kl, independently
+    of the others (counting with unequal detectors, where the multinomial
+    model of Eq. (likelihood) no longer holds).  Truth: a Haar pure state with
+    white noise."""
+    rng = np.random.default_rng([DATA_SEED, 93, Q, index])
+    D = 2 ** Q
+    st = _noisy_pure(Q, haar_vector(D, rng), white)
+    eta = np.ones(D)
+    for l in range(D):
+        for q in range(Q):
+            eta[l] *= efficiency[(l >> (Q - 1 - q)) & 1]
+    intensity = np.tile(shots * eta, (3 ** Q, 1))
+    mean = intensity * np.clip(outcome_distribution(st), 0.0, None)
+    counts = rng.poisson(mean).astype(np.int64)
+    return PoissonProblem(f"poisson_{Q}", Q, counts, intensity, st, CHAIN_SEED + 400 + Q)
+
+
 def sic_qubit_problem(shots=4000, white=0.1) -> PovmProblem:
     """The qubit SIC-POVM: Pi_m = (I + n_m . sigma) / 4 with n_m the vertices
     of a regular tetrahedron; the outcome probabilities of a state with Bloch

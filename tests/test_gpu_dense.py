@@ -3,12 +3,14 @@ FP64 oracle.
 
 FP64: the same bars as the Kronecker path (log L of given states within
 1e-12 relative; chains in lockstep within 1e-10).  FP32 and BF16x3: p is
-accumulated in FP32, so each p carries a relative error of order
-sqrt(K) 2^-24 and log L an error of order sum_m c_m |dp_m / p_m|; the tests
-bound |d log L| by 1e-6 * sum(c) (about 0.08 at 4 qubits) and check the
-special case that must be exact in any precision (zero counts: every
-proposal accepted, the same trajectories as FP64).
+accumulated in FP32 and log2 p taken by the hardware FP32 logarithm; log L
+of given states must lie within the a-priori rounding bound of that
+arithmetic (_dense_bound), chains within 1e-6 * sum(c) (about 0.08 at 4
+qubits) while their decisions agree; and the special case that must be exact
+in any precision holds (zero counts: every proposal accepted, the same
+trajectories as FP64).
 """
+import itertools
 import numpy as np
 import pytest
 import torch
@@ -29,6 +31,44 @@ def _need_gpu():
 def _problem(Q):
     return {1: synth.make_problem("c1"), 2: synth.make_problem("c2"), 3: synth.make_problem("w_3"),
             4: synth.make_problem("c3")}[Q]
+
+
+def _abs_eigvec(Q, k, l):
+    """|e_kl| entrywise: the product eigenvector of setting k, outcome l
+    (X and Y eigenvectors have entries of modulus 1/sqrt 2, Z ones 1 or 0)."""
+    s = [(k // 3 ** (Q - 1 - q)) % 3 for q in range(Q)]
+    b = [(l >> (Q - 1 - q)) & 1 for q in range(Q)]
+    v = np.ones(1)
+    for q in range(Q):
+        f = np.array([2 ** -0.5, 2 ** -0.5]) if s[q] < 2 else np.eye(2)[b[q]]
+        v = np.kron(v, f)
+    return v
+
+
+def _dense_bound(Q, counts, rho, precision):
+    """A-priori bound on |log L - log L_fp64| of the reduced-precision dense
+    forms: each p_m = sum_k M_mk vec(rho)_k is an FP32 sum of n_t exact
+    products (n_t = D^2 for FP32, 3 D^2 padded for BF16x3) of operands
+    rounded to relative 2^-24 (FP32 rounding of rho, or what the three BF16
+    parts leave), so |dp_m| <= (n_t 2^-23 + 2^-24) A_m with
+    A_m = sum_ab |Pi_ab| |rho_ab| = |e_m|^T |rho| |e_m| (Higham ch. 3, with
+    u = 2^-23 covering truncating adds); the FP32 logarithm adds at most
+    2^-22 |ln p| + 2^-24; each term contributes n_m (|dp_m| / p_m + that)."""
+    D, K = 2 ** Q, 3 ** Q
+    n_t = D * D if precision == "fp32" else 3 * ((D * D + 31) // 32 * 32)
+    g = n_t * 2.0 ** -23 + 2.0 ** -24
+    p = O.probs(Q, rho).ravel()
+    c = np.asarray(counts, dtype=np.float64).ravel()
+    absr = np.abs(rho)
+    total = 0.0
+    for k, l in itertools.product(range(K), range(D)):
+        m = k * D + l
+        if c[m] == 0:
+            continue
+        e = _abs_eigvec(Q, k, l)
+        pm = max(p[m], 2.0 ** -126)
+        total += c[m] * (g * (e @ absr @ e) / pm + 2.0 ** -22 * abs(np.log(pm)) + 2.0 ** -24)
+    return total
 
 
 def _loglik(P, rhos, precision):
@@ -56,7 +96,10 @@ def test_dense_loglik_of_given_states(Q, precision):
     if precision == "fp64":
         assert np.all(err <= 1e-12 * np.abs(want))
     else:
-        assert np.all(err <= 1e-6 * prob.counts.sum())
+        bound = np.array([_dense_bound(Q, prob.counts, r, precision) for r in rhos])
+        print(f"  max err / a-priori bound = {np.max(err / bound):.3e}", flush=True)
+        assert np.all(err <= bound)
+        assert np.all(err <= 1e-6 * prob.counts.sum())   # the stated tolerance of the reduced forms
 
 
 @pytest.mark.parametrize("Q", [1, 2, 3, 4])
@@ -106,3 +149,32 @@ def test_reduced_precision_chain_error(precision):
         worst = max(worst, err.max())
     print(f"[{precision}] max |dlogL| over lockstep proposals: {worst:.3e}", flush=True)
     assert worst <= 1e-6 * prob.counts.sum()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_dense_loglik_zero_probability_marks_only_its_matrix(precision):
+    """A matrix with p = 0 on a projector that carries counts has log L = -inf
+    (FP64; the reduced forms clamp p at 2^-126 and stay finite); every other
+    matrix of its workgroup keeps its own value.  70 matrices span two
+    workgroups of 64."""
+    Q = 2
+    prob = _problem(Q)
+    D = 2 ** Q
+    rng = np.random.default_rng(77)
+    rhos = np.stack([synth.random_density_matrix(D, rng, rank=2) for _ in range(70)])
+    pure = np.zeros((D, D), dtype=complex)
+    pure[0, 0] = 1.0                     # |00><00|: p = 0 for outcome 11 of the ZZ setting
+    for i in (5, 66):
+        rhos[i] = pure
+    want = np.array([O.loglik(Q, prob.counts, O.probs(Q, r)) for r in rhos])
+    P = qst.Problem(Q, prob.counts)
+    got = _loglik(P, rhos, precision)
+    ok = np.ones(70, dtype=bool)
+    ok[[5, 66]] = False
+    assert np.all(np.isneginf(want[~ok]))
+    if precision == "fp64":
+        assert np.all(np.isneginf(got[~ok]))
+        assert np.all(np.abs(got[ok] - want[ok]) <= 1e-12 * np.abs(want[ok]))
+    else:
+        assert np.all(np.isfinite(got))
+        assert np.all(np.abs(got[ok] - want[ok]) <= 1e-6 * prob.counts.sum())
