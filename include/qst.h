@@ -291,6 +291,22 @@ qst_status qst_pool_moments_static(const qst_problem* p, double* out, int64_t* n
 qst_status qst_chain_state(const qst_problem* p, double* x, double* loglik, double* beta,
                            int64_t* n_stored);
 
+/* Restore the chains' state from HOST buffers (a checkpoint written with
+ * qst_chain_state and qst_chain_moments, or any state): step >= 0 sets the
+ * number of steps the handle has run (the next resumed run starts at step
+ * step + 1; -1 keeps it); x [R][d] (a non-finite entry makes that chain's
+ * log L and every proposal of it non-finite, so it never accepts and
+ * qst_run_stats.nonfinite_chains counts it), beta [R] in (0, 1], s1 and s2 [R][D*D]
+ * (packed, as qst_chain_moments gives them) and n_stored [R]; NULL keeps the
+ * handle's own.  Log L and rho of a new x are evaluated at the start of the
+ * next qst_run_chains with resume = 1 (a step-free launch of the chain
+ * kernel before the run).  The adaptation window's acceptance count is kept,
+ * so a checkpoint taken at a multiple of M_A restores exactly: resumed, it
+ * gives the chains of an uninterrupted run (with the same launch shape).
+ * QST_ERR_STATE before any run (a run of 0 steps allocates R chains). */
+qst_status qst_set_chain_state(qst_problem* p, int64_t step, const double* x, const double* beta, const double* s1,
+                               const double* s2, const int64_t* n_stored);
+
 /* Each chain's own moment sums of Eq. (BME2) to HOST buffers (NULL to
  * skip): s1 [R][D*D] = sum of the packed rho of its stored samples, s2 the
  * element-wise sum of squares (packed real form, see above); with n_stored

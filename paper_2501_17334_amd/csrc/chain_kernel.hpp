@@ -82,7 +82,8 @@ struct ChainArgs {
     int64_t adapt_until;
     int32_t thin;
     int32_t adapt_every;
-    int32_t init;           // 1: draw y^0 (step 0) and evaluate it first
+    int32_t init;           // 1: draw y^0 (step 0) and evaluate it first; 2: evaluate the stored state
+                            //    (log L, packed rho) and keep the rest of it
     int32_t poisson;        // 1: Poisson counts: log L -= sum_p W[p] rho_p, W = nd + KD (packed)
     double beta0;
     double adapt_lo, adapt_hi, adapt_factor;
@@ -1468,7 +1469,30 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     };
 
     // ---- load or initialise the chain state ----
-    if (A.init) {
+    if (A.init == 2) {
+        // a state set from outside (checkpoint, restart): y from memory, its
+        // log L and packed rho evaluated here, everything else kept
+        for (int i = lane; i < d; i += G) ybuf[i] = A.x[c * d + i];
+        sync();
+        ll = evaluate();
+#pragma unroll
+        for (int e = 0; e < S::NYL; ++e) {
+            const int i = lane + G * e;
+            y[e] = i < d ? ybuf[i] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < S::NPL; ++e) {
+            const int p = packed_slot<Q, G>(lane, e);
+            const bool ok = p < D2;
+            rc[e] = ok ? rhoP[p] : 0.0;
+            s1[e] = ok ? A.s1[c * D2 + p] : 0.0;
+            s2[e] = ok ? A.s2[c * D2 + p] : 0.0;
+        }
+        beta = A.beta[c];
+        acc_w = A.acc_win[c];
+        nst = A.n_stored[c];
+        sync();
+    } else if (A.init) {
         draw_all(0);                     // y^0 ~ N(0, I): Algorithm 2, first line
         __syncthreads();
         ll = evaluate();

@@ -536,6 +536,7 @@ struct qst_problem {
     // chain state
     int64_t R = 0;
     int64_t chain0 = 0;     // index of chain 0 of this handle within its problem (qst_run_desc.chain_offset)
+    bool reeval = false;    // qst_set_chain_state wrote x: evaluate log L and rho before the next run
     int64_t step = 0;
     bool have_run = false;
     double *x = nullptr, *ll = nullptr, *beta = nullptr, *rho = nullptr, *s1 = nullptr, *s2 = nullptr;
@@ -875,7 +876,7 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r, bool problem_wid
     a.adapt_until = r.adapt_until;
     a.thin = r.thin;
     a.adapt_every = r.adapt_every;
-    a.init = r.resume ? 0 : 1;
+    a.init = r.resume ? (p->reeval ? 2 : 0) : 1;
     a.poisson = p->poisson ? 1 : 0;
     a.beta0 = r.beta0;
     a.adapt_lo = r.adapt_lo;
@@ -1147,6 +1148,30 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
         DeviceGuard g(dev);
         hipStream_t s = static_cast<hipStream_t>(runs[0].stream);
         for (int i = 0; i < n_problems; ++i) prepare_state(problems[i], runs[i]);
+        // states set by qst_set_chain_state: log L and packed rho evaluated by
+        // a step-free launch of the chain kernel, then the run resumes from them
+        for (int i = 0; i < n_problems; ++i) {
+            qst_problem* p = problems[i];
+            if (!p->reeval) continue;
+            if (runs[i].resume) {
+                qst_run_desc r0 = runs[i];
+                r0.n_steps = 0;
+                r0.surrogate = nullptr;
+                r0.trace_chains = 0;
+                r0.record_every = r0.record_chains = 0;
+                r0.pair_every = r0.pair_chains = 0;
+                const qst::ChainArgs a0 = make_args(p, r0);
+                if (p->param == QST_PARAM_BURES)
+                    launch_chains_bures(p->Q, static_cast<int>(p->precision), a0, p->chain0, s);
+                else if (p->param == QST_PARAM_DIRICHLET)
+                    launch_chains_dirichlet(p->Q, static_cast<int>(p->precision), a0, p->chain0, s);
+                else
+                    launch_chains(p->Q, current_shape(p->Q),
+                                  p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
+                                  static_cast<int>(p->precision), a0, p->chain0, s);
+            }
+            p->reeval = false;
+        }
         if (n_problems == 1 && runs[0].surrogate) {
             launch_da(problems[0], runs[0], s);
         } else if (n_problems == 1) {
@@ -1322,6 +1347,32 @@ qst_status qst_chain_state(const qst_problem* p, double* x, double* loglik, doub
         if (beta) hip_check(hipMemcpy(beta, p->beta, sizeof(double) * p->R, hipMemcpyDeviceToHost), "state copy");
         if (n_stored)
             hip_check(hipMemcpy(n_stored, p->nst, sizeof(int64_t) * p->R, hipMemcpyDeviceToHost), "state copy");
+    });
+}
+
+qst_status qst_set_chain_state(qst_problem* p, int64_t step, const double* x, const double* beta, const double* s1,
+                               const double* s2, const int64_t* n_stored)
+{
+    return guarded([&] {
+        if (!p) fail(QST_ERR_INVALID, "NULL handle");
+        if (!p->have_run) fail(QST_ERR_STATE, "no chains yet: run (n_steps 0 allocates and initialises them) first");
+        if (step < -1) fail(QST_ERR_INVALID, "step must be >= 0 (or -1 to keep)");
+        if (beta)
+            for (int64_t c = 0; c < p->R; ++c)
+                if (!(beta[c] > 0.0 && beta[c] <= 1.0)) fail(QST_ERR_INVALID, "beta must lie in (0, 1]");
+        if (n_stored)
+            for (int64_t c = 0; c < p->R; ++c)
+                if (n_stored[c] < 0) fail(QST_ERR_INVALID, "n_stored must be >= 0");
+        DeviceGuard g(p->device);
+        if (p->last_stream) hip_check(hipStreamSynchronize(p->last_stream), "state synchronize");
+        const size_t R = static_cast<size_t>(p->R), m = R * p->D2;
+        if (x) hip_check(hipMemcpy(p->x, x, sizeof(double) * R * p->d, hipMemcpyHostToDevice), "state copy");
+        if (beta) hip_check(hipMemcpy(p->beta, beta, sizeof(double) * R, hipMemcpyHostToDevice), "state copy");
+        if (s1) hip_check(hipMemcpy(p->s1, s1, sizeof(double) * m, hipMemcpyHostToDevice), "state copy");
+        if (s2) hip_check(hipMemcpy(p->s2, s2, sizeof(double) * m, hipMemcpyHostToDevice), "state copy");
+        if (n_stored) hip_check(hipMemcpy(p->nst, n_stored, sizeof(int64_t) * R, hipMemcpyHostToDevice), "state copy");
+        if (step >= 0) p->step = step;
+        if (x) p->reeval = true;
     });
 }
 

@@ -88,6 +88,8 @@ def lib():
         L.qst_chain_state.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.qst_chain_moments.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.qst_set_chain_state.argtypes = [vp, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.qst_loglik.argtypes = [vp, vp, C.c_int64, vp, C.c_int, C.c_int, vp]
         L.qst_acf.argtypes = [vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
         L.qst_set_launch_shape.argtypes = [C.c_int32, C.c_int32, C.c_int32]
@@ -112,6 +114,7 @@ def lib():
         L.qst_last_error.restype = C.c_char_p
         L.qst_version.restype = C.c_char_p
         for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state", "qst_chain_moments",
+                  "qst_set_chain_state",
                   "qst_loglik", "qst_acf", "qst_set_launch_shape", "qst_get_launch_shape",
                   "qst_list_launch_shapes", "qst_mlp_create", "qst_mlp_set_params", "qst_mlp_get_params",
                   "qst_mlp_gradients", "qst_mlp_train_step", "qst_mlp_predict", "qst_mlp_surrogate",
@@ -330,6 +333,27 @@ class Problem:
         _check(lib().qst_chain_state(self._h, _f64(x), _f64(ll), _f64(beta),
                                      nst.ctypes.data_as(C.POINTER(C.c_int64))))
         return x, ll, beta, nst
+
+    def set_state(self, x=None, beta=None, step=-1, s1=None, s2=None, n_stored=None):
+        """qst_set_chain_state from host arrays (None keeps): x [R, d],
+        beta [R], s1 / s2 [R, D, D] (as moments() returns them), n_stored [R];
+        step >= 0 sets the steps already run.  The next run with resume=True
+        evaluates a new x first."""
+        R, D = self.n_chains, self.D
+
+        def arr(a, shape, dtype=np.float64):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dtype)
+            if a.shape != shape:
+                raise ValueError(f"expected shape {shape}, got {a.shape}")
+            return a
+        xa, ba = arr(x, (R, self.d)), arr(beta, (R,))
+        s1a, s2a = arr(s1, (R, D, D)), arr(s2, (R, D, D))
+        na = arr(n_stored, (R,), np.int64)
+        f = lambda a: _f64(a) if a is not None else None
+        _check(lib().qst_set_chain_state(self._h, int(step), f(xa), f(ba), f(s1a), f(s2a),
+                                         na.ctypes.data_as(C.POINTER(C.c_int64)) if na is not None else None))
 
     def moments(self):
         """qst_chain_moments: per-chain sums (s1 [R, D, D], s2 [R, D, D]) of the
