@@ -89,9 +89,11 @@ typedef enum {
 
 /* How p_kl = Tr(Lambda_kl rho) is formed. */
 typedef enum {
-    QST_PATH_AUTO = 0,   /* the Kronecker route, except for QST_BF16X3 (dense) */
+    QST_PATH_AUTO = 0,   /* the autotuner's choice for the qubit count and precision
+                            (qst_set_auto_path); by default the Kronecker route,
+                            except for QST_BF16X3 (dense) */
     QST_PATH_DENSE = 1,  /* GEMM of packed vec(rho) against the KD x D^2 Pauli matrix
-                            on MFMA; 1..4 qubits */
+                            on MFMA; chains 1..4 qubits, qst_loglik 1..5 */
     QST_PATH_KRON = 2    /* per-qubit (Kronecker) route: Pauli coefficients, then a
                             2^Q-point Walsh-Hadamard transform per setting; FP64 or
                             FP32 (QST_ERR_UNSUPPORTED for QST_BF16X3) */
@@ -254,6 +256,12 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems,
  * autotuner (paper_2501_17334_amd/tune.py) times them and installs the
  * fastest.  Process-wide setting, not thread-safe. */
 qst_status qst_set_launch_shape(int32_t n_qubits, int32_t team, int32_t workgroup);
+/* The path QST_PATH_AUTO takes for n_qubits and a precision (KRON or DENSE;
+ * by default the Kronecker route, except BF16x3, which is dense only): the
+ * autotuner times the chain step on both paths and installs the faster.
+ * Applies to problems created afterwards.  Process-wide, not thread-safe. */
+qst_status qst_set_auto_path(int32_t n_qubits, qst_precision precision, qst_path path);
+qst_status qst_get_auto_path(int32_t n_qubits, qst_precision precision, qst_path* path);
 qst_status qst_get_launch_shape(int32_t n_qubits, int32_t* team, int32_t* workgroup);
 /* The compiled shapes for n_qubits: up to `capacity` (team, workgroup) pairs
  * into the host arrays; *count receives how many exist. */

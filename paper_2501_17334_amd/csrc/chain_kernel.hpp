@@ -1714,7 +1714,8 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
 
 // ---------------------------------------------------------------------------
 // Eq. (likelihood) for n given density matrices on the dense path, alone
-// (qst_loglik): 64 matrices per 1024-thread workgroup (48 for BF16x3), so
+// (qst_loglik), 1..5 qubits: 64 matrices per 1024-thread workgroup (48 for
+// BF16x3; at 5 qubits 32 in FP32, 16 otherwise, what LDS holds), so
 // that each fragment of M, streamed from L2, feeds four (three) MFMAs, one
 // per 16-column block of matrices, instead of one.  Their B operands sit in
 // LDS in the precision's format, one padded row per matrix; wave w computes
@@ -1727,7 +1728,9 @@ __global__ __launch_bounds__(WG) void k_loglik(const double* __restrict__ nd, co
 template <int Q, int PREC>
 struct DenseAloneShape {
     using DS = DenseShape<Q>;
-    static constexpr int kStates = PREC == kPrecBF16x3 ? 48 : 64;   // matrices per workgroup
+    // matrices per workgroup: as many 16-column blocks as the operands of all
+    // D^2 values of k leave room for in LDS (5 qubits: 1024 values per matrix)
+    static constexpr int kStates = Q <= 4 ? (PREC == kPrecBF16x3 ? 48 : 64) : (PREC == kPrecF32 ? 32 : 16);
     static constexpr int kBlocks = kStates / 16;       // 16-column MFMA blocks
     // B row stride in elements of the operand type, padded against LDS bank
     // conflicts between the 16 rows one MFMA reads

@@ -319,6 +319,15 @@ Shape g_shape[7] = {{0, 0}, {8, 64}, {16, 64}, {32, 64}, {64, 256}, {256, 256}, 
 
 Shape current_shape(int Q) { return g_shape[Q]; }
 
+// Path that QST_PATH_AUTO takes per qubit count and precision: the Kronecker
+// route, except BF16x3 (dense only); the autotuner installs its measured
+// choice through qst_set_auto_path.
+qst_path g_auto_path[7][3] = {
+    {QST_PATH_KRON, QST_PATH_KRON, QST_PATH_DENSE}, {QST_PATH_KRON, QST_PATH_KRON, QST_PATH_DENSE},
+    {QST_PATH_KRON, QST_PATH_KRON, QST_PATH_DENSE}, {QST_PATH_KRON, QST_PATH_KRON, QST_PATH_DENSE},
+    {QST_PATH_KRON, QST_PATH_KRON, QST_PATH_DENSE}, {QST_PATH_KRON, QST_PATH_KRON, QST_PATH_DENSE},
+    {QST_PATH_KRON, QST_PATH_KRON, QST_PATH_DENSE}};
+
 bool shape_compiled(int Q, Shape sh)
 {
     for (const Shape& c : kShapes[Q])
@@ -436,8 +445,9 @@ void launch_loglik_dense(int Q, int prec, const double* nd, const void* mfrag, c
     QST_DENSE(2, kPrecF64) QST_DENSE(2, kPrecF32) QST_DENSE(2, kPrecBF16x3)
     QST_DENSE(3, kPrecF64) QST_DENSE(3, kPrecF32) QST_DENSE(3, kPrecBF16x3)
     QST_DENSE(4, kPrecF64) QST_DENSE(4, kPrecF32) QST_DENSE(4, kPrecBF16x3)
+    QST_DENSE(5, kPrecF64) QST_DENSE(5, kPrecF32) QST_DENSE(5, kPrecBF16x3)
 #undef QST_DENSE
-    fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
+    fail(QST_ERR_UNSUPPORTED, "the dense contraction is built for 1..5 qubits");
 }
 
 template <int PREC>
@@ -520,7 +530,7 @@ struct qst_problem {
     const void* fragments(int prec)
     {
         if (!mfrag[prec]) {
-            if (Q > 4) fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
+            if (Q > 5) fail(QST_ERR_UNSUPPORTED, "the dense contraction is built for 1..5 qubits");
             const std::vector<uint8_t> f =
                 matrix_fragments(Q, povm_M.empty() ? pauli_matrix_packed(Q) : povm_M, prec);
             void* d = dev_alloc<uint8_t>(f.size());
@@ -709,12 +719,13 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out)
         p->KD = p->K * p->D;
         p->device = desc->device;
         p->precision = desc->precision;
-        p->path = desc->path == QST_PATH_AUTO ? (desc->precision == QST_BF16X3 ? QST_PATH_DENSE : QST_PATH_KRON)
-                                              : desc->path;
+        p->path = desc->path == QST_PATH_AUTO ? g_auto_path[Q][desc->precision] : desc->path;
         if (p->path == QST_PATH_KRON && p->precision == QST_BF16X3)
             fail(QST_ERR_UNSUPPORTED, "the Kronecker path runs in FP64 or FP32; BF16x3 needs QST_PATH_DENSE");
         if (p->path == QST_PATH_DENSE && Q > 4)
-            fail(QST_ERR_UNSUPPORTED, "dense contraction is built for 1..4 qubits only");
+            fail(QST_ERR_UNSUPPORTED,
+                 "the dense chain step is built for 1..4 qubits (16 chains of a workgroup share the MFMA tiles, "
+                 "and at 5 qubits their states do not fit in LDS); qst_loglik takes QST_PATH_DENSE up to 5 qubits");
         if (desc->povm) {
             // user POVM elements: the dense contraction against their matrix
             if (desc->n_povm < 1 || desc->n_povm > p->KD)
@@ -1221,6 +1232,30 @@ qst_status qst_set_launch_shape(int32_t n_qubits, int32_t team, int32_t workgrou
         const Shape sh{team, workgroup};
         if (!shape_compiled(n_qubits, sh)) fail(QST_ERR_UNSUPPORTED, "no chain kernel compiled for this shape");
         g_shape[n_qubits] = sh;
+    });
+}
+
+qst_status qst_set_auto_path(int32_t n_qubits, qst_precision precision, qst_path path)
+{
+    return guarded([&] {
+        if (n_qubits < 1 || n_qubits > 6) fail(QST_ERR_INVALID, "n_qubits must be in 1..6");
+        if (precision != QST_FP64 && precision != QST_FP32 && precision != QST_BF16X3)
+            fail(QST_ERR_INVALID, "unknown precision");
+        if (path != QST_PATH_DENSE && path != QST_PATH_KRON) fail(QST_ERR_INVALID, "path must be DENSE or KRON");
+        if (path == QST_PATH_KRON && precision == QST_BF16X3)
+            fail(QST_ERR_UNSUPPORTED, "the Kronecker path runs in FP64 or FP32");
+        if (path == QST_PATH_DENSE && n_qubits > 4) fail(QST_ERR_UNSUPPORTED, "the dense chain step stops at 4 qubits");
+        g_auto_path[n_qubits][precision] = path;
+    });
+}
+
+qst_status qst_get_auto_path(int32_t n_qubits, qst_precision precision, qst_path* path)
+{
+    return guarded([&] {
+        if (n_qubits < 1 || n_qubits > 6 || !path) fail(QST_ERR_INVALID, "bad argument");
+        if (precision != QST_FP64 && precision != QST_FP32 && precision != QST_BF16X3)
+            fail(QST_ERR_INVALID, "unknown precision");
+        *path = g_auto_path[n_qubits][precision];
     });
 }
 

@@ -94,6 +94,8 @@ def lib():
         L.qst_acf.argtypes = [vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
         L.qst_set_launch_shape.argtypes = [C.c_int32, C.c_int32, C.c_int32]
         L.qst_get_launch_shape.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.qst_set_auto_path.argtypes = [C.c_int32, C.c_int, C.c_int]
+        L.qst_get_auto_path.argtypes = [C.c_int32, C.c_int, C.POINTER(C.c_int)]
         L.qst_list_launch_shapes.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
                                              C.POINTER(C.c_int32)]
         L.qst_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(vp)]
@@ -114,7 +116,7 @@ def lib():
         L.qst_last_error.restype = C.c_char_p
         L.qst_version.restype = C.c_char_p
         for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state", "qst_chain_moments",
-                  "qst_set_chain_state",
+                  "qst_set_chain_state", "qst_set_auto_path", "qst_get_auto_path",
                   "qst_loglik", "qst_acf", "qst_set_launch_shape", "qst_get_launch_shape",
                   "qst_list_launch_shapes", "qst_mlp_create", "qst_mlp_set_params", "qst_mlp_get_params",
                   "qst_mlp_gradients", "qst_mlp_train_step", "qst_mlp_predict", "qst_mlp_surrogate",
@@ -134,7 +136,11 @@ def _install_tuned_shapes():
     with open(path) as f:
         table = json.load(f)
     for q, ent in table.items():
-        _lib.qst_set_launch_shape(int(q), int(ent["team"]), int(ent["workgroup"]))
+        if q.isdigit():
+            _lib.qst_set_launch_shape(int(q), int(ent["team"]), int(ent["workgroup"]))
+    for q, per in table.get("paths", {}).items():
+        for prec, ent in per.items():
+            _lib.qst_set_auto_path(int(q), _PREC[prec], _PATH[ent["path"]])
 
 
 def _check(status):
@@ -487,6 +493,16 @@ def get_launch_shape(n_qubits):
     t, w = C.c_int32(), C.c_int32()
     _check(lib().qst_get_launch_shape(n_qubits, C.byref(t), C.byref(w)))
     return t.value, w.value
+
+
+def set_auto_path(n_qubits, precision, path):
+    _check(lib().qst_set_auto_path(n_qubits, _PREC[precision], _PATH[path]))
+
+
+def get_auto_path(n_qubits, precision):
+    v = C.c_int()
+    _check(lib().qst_get_auto_path(n_qubits, _PREC[precision], C.byref(v)))
+    return {PATH_AUTO: "auto", PATH_DENSE: "dense", PATH_KRON: "kron"}[v.value]
 
 
 def list_launch_shapes(n_qubits):

@@ -1,11 +1,19 @@
-"""Autotuner for the chain kernel's launch shape (team size G, workgroup WG)
-per qubit count.
+"""Autotuner of the chain kernel: launch shape and contraction path.
 
-For every compiled shape of a qubit count it runs the same synthetic problem
-(Haar pure state + 10% white noise, 1024 shots per setting) for a fixed number
-of chains and steps, times the launch with HIP events, and keeps the fastest
-shape.  The table is written as JSON next to the library and installed in the
-library through qst_set_launch_shape; `load()` installs a saved table.
+Shapes: for every compiled (team size G, workgroup WG) of a qubit count it
+runs the same synthetic problem (Haar pure state + 10% white noise, 1024
+shots per setting) for a fixed number of chains and steps, times the launch
+with HIP events, and keeps the fastest shape (qst_set_launch_shape).
+
+Paths: per qubit count (1..4) and precision (FP64, FP32) it times the chain
+step on the Kronecker route and on the dense MFMA contraction, each with its
+own launch shape, and makes the faster one what QST_PATH_AUTO takes
+(qst_set_auto_path); BF16x3 exists on the dense path only.  Beside it, the
+contraction alone (qst_loglik on given states, 1..5 qubits) on both paths,
+so the choice can be read against the raw contraction rates.
+
+The table is written as JSON next to the library; the binding installs it
+when the library is loaded, and `load()` installs a saved table.
 """
 from __future__ import annotations
 
@@ -46,7 +54,73 @@ def time_shape(Q, shape, chains, steps):
     return chains * steps / (ms / 1e3)
 
 
-def tune(qubits=(1, 2, 3, 4, 5, 6), out=TABLE, verbose=True):
+def time_path(Q, path, precision, chains, steps):
+    """Chain-steps/s of plain pCN on `path` in `precision` (the path's own
+    launch shape: the tuned one for Kronecker, 16 chains per workgroup dense)."""
+    import torch
+    prob = _problem(Q)
+    P = qst.Problem(Q, prob.counts, precision=precision, path=path)
+    cfg = qst.RunConfig(n_chains=chains, n_steps=steps, seed=prob.seed, beta0=0.01, adapt_every=0)
+    P.run(qst.RunConfig(n_chains=chains, n_steps=1, seed=prob.seed, beta0=0.01, adapt_every=0), stats=False)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    P.run(cfg, stats=False)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    P.close()
+    return chains * steps / (ms / 1e3)
+
+
+def contraction_rates(Q, n_states=None, reps=3):
+    """qst_loglik on n_states given density matrices: matrices/s per (path,
+    precision) -- the probability contraction and log-likelihood alone."""
+    import numpy as np
+    import torch
+    prob = _problem(Q)
+    D = 2 ** Q
+    n = n_states or {1: 65536, 2: 65536, 3: 65536, 4: 65536, 5: 8192}[Q]
+    rng = np.random.default_rng(5)
+    base = np.stack([synth.random_density_matrix(D, rng) for _ in range(16)])
+    rhos = np.ascontiguousarray(np.stack([base.real, base.imag], -1)[np.arange(n) % 16])
+    dev = torch.from_numpy(rhos).cuda()
+    out = torch.zeros(n, dtype=torch.float64, device="cuda")
+    P = qst.Problem(Q, prob.counts)
+    res = {}
+    for path, prec in (("kron", "fp64"), ("kron", "fp32"), ("dense", "fp64"), ("dense", "fp32"), ("dense", "bf16x3")):
+        P.loglik(dev, out, path=path, precision=prec)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            P.loglik(dev, out, path=path, precision=prec)
+        b.record()
+        torch.cuda.synchronize()
+        res[f"{path}_{prec}"] = n / (a.elapsed_time(b) / reps / 1e3)
+    P.close()
+    return res
+
+
+def tune_paths(qubits=(1, 2, 3, 4), verbose=True):
+    """The faster path of the chain step per qubit count and precision,
+    installed for QST_PATH_AUTO; returns the measured rates."""
+    out = {}
+    for Q in qubits:
+        chains, steps = WORK[Q]
+        out[str(Q)] = {}
+        for prec in ("fp64", "fp32"):
+            kr = time_path(Q, "kron", prec, chains, steps)
+            de = time_path(Q, "dense", prec, chains, steps)
+            best = "kron" if kr >= de else "dense"
+            qst.set_auto_path(Q, prec, best)
+            out[str(Q)][prec] = {"path": best, "kron_chain_steps_per_s": kr, "dense_chain_steps_per_s": de}
+            if verbose:
+                print(f"[tune] Q={Q} {prec}: kron {kr:.4g}, dense {de:.4g} chain-steps/s -> {best}", flush=True)
+    return out
+
+
+def tune(qubits=(1, 2, 3, 4, 5, 6), out=TABLE, verbose=True, paths=True):
     table = {}
     for Q in qubits:
         chains, steps = WORK[Q]
@@ -62,6 +136,14 @@ def tune(qubits=(1, 2, 3, 4, 5, 6), out=TABLE, verbose=True):
         qst.set_launch_shape(Q, *best[0])
         table[str(Q)] = {"team": best[0][0], "workgroup": best[0][1], "chain_steps_per_s": best[1],
                          "trials": trials, "chains": chains, "steps": steps}
+    if paths:
+        table["paths"] = tune_paths(tuple(q for q in qubits if q <= 4), verbose)
+        table["contraction_states_per_s"] = {}
+        for Q in (q for q in qubits if q <= 5):
+            table["contraction_states_per_s"][str(Q)] = r = contraction_rates(Q)
+            if verbose:
+                print(f"[tune] Q={Q} contraction alone: " + ", ".join(f"{k} {v:.3g}" for k, v in r.items()),
+                      flush=True)
     if out:
         with open(out, "w") as f:
             json.dump(table, f, indent=1)
@@ -75,10 +157,15 @@ def load(path=TABLE):
     with open(path) as f:
         table = json.load(f)
     for q, ent in table.items():
+        if not q.isdigit():
+            continue
         try:
             qst.set_launch_shape(int(q), int(ent["team"]), int(ent["workgroup"]))
         except qst.QstError:
             pass
+    for q, per in table.get("paths", {}).items():
+        for prec, ent in per.items():
+            qst.set_auto_path(int(q), prec, ent["path"])
     return table
 
 

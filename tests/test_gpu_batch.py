@@ -158,3 +158,23 @@ def test_launch_shapes_roundtrip():
         assert cur in shapes
     with pytest.raises(qst.QstError):
         qst.set_launch_shape(4, 3, 64)
+
+
+def test_auto_path_roundtrip():
+    saved = qst.get_auto_path(3, "fp64")
+    try:
+        qst.set_auto_path(3, "fp64", "dense")
+        assert qst.get_auto_path(3, "fp64") == "dense"
+        p = synth.make_problem("w_3")
+        P = qst.Problem(3, p.counts)               # path "auto": now the dense chain step
+        st = P.run(qst.RunConfig(n_chains=16, n_steps=5, seed=1, beta0=0.05))
+        assert st["proposed"] == 80
+    finally:
+        qst.set_auto_path(3, "fp64", saved)
+    assert qst.get_auto_path(2, "bf16x3") == "dense"
+    for q, prec, path, status in ((5, "fp64", "dense", qst.QST_ERR_UNSUPPORTED),
+                                  (2, "bf16x3", "kron", qst.QST_ERR_UNSUPPORTED),
+                                  (7, "fp64", "kron", qst.QST_ERR_INVALID)):
+        with pytest.raises(qst.QstError) as e:
+            qst.set_auto_path(q, prec, path)
+        assert e.value.status == status

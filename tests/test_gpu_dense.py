@@ -2,7 +2,7 @@
 FP64 oracle.
 
 FP64: the same bars as the Kronecker path (log L of given states within
-1e-12 relative; chains in lockstep within 1e-10).  FP32 and BF16x3: p is
+1e-12 relative, 1..5 qubits; chains in lockstep within 1e-10, 1..4 qubits).  FP32 and BF16x3: p is
 accumulated in FP32 and log2 p taken by the hardware FP32 logarithm; log L
 of given states must lie within the a-priori rounding bound of that
 arithmetic (_dense_bound), chains within 1e-6 * sum(c) (about 0.08 at 4
@@ -30,7 +30,7 @@ def _need_gpu():
 
 def _problem(Q):
     return {1: synth.make_problem("c1"), 2: synth.make_problem("c2"), 3: synth.make_problem("w_3"),
-            4: synth.make_problem("c3")}[Q]
+            4: synth.make_problem("c3"), 5: synth.make_problem("c4")}[Q]
 
 
 def _abs_eigvec(Q, k, l):
@@ -79,14 +79,14 @@ def _loglik(P, rhos, precision):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("Q", [1, 2, 3, 4])
+@pytest.mark.parametrize("Q", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_dense_loglik_of_given_states(Q, precision):
     print(f"[dense loglik] Q={Q} {precision}", flush=True)
     prob = _problem(Q)
     D = 2 ** Q
     rng = np.random.default_rng(2000 + Q)
-    n = 37
+    n = 37 if Q < 5 else 21          # 21 five-qubit matrices span two workgroups of 16 (FP64, BF16x3)
     rhos = np.stack([synth.random_density_matrix(D, rng, rank=int(rng.integers(1, D + 1))) for _ in range(n)])
     want = np.array([O.loglik(Q, prob.counts, O.probs(Q, r)) for r in rhos])
     P = qst.Problem(Q, prob.counts)
@@ -178,3 +178,12 @@ def test_dense_loglik_zero_probability_marks_only_its_matrix(precision):
     else:
         assert np.all(np.isfinite(got))
         assert np.all(np.abs(got[ok] - want[ok]) <= 1e-6 * prob.counts.sum())
+
+
+def test_dense_chain_step_refused_at_five_qubits():
+    """qst_loglik takes the dense path up to 5 qubits; the dense chain step
+    (16 chains of a workgroup share the MFMA tiles) stops at 4."""
+    prob = _problem(5)
+    with pytest.raises(qst.QstError) as e:
+        qst.Problem(5, prob.counts, path="dense")
+    assert e.value.status == qst.QST_ERR_UNSUPPORTED
