@@ -573,8 +573,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the chains need no "
-              f"communication, see DESIGN.md for how the run would shard)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported. The chains need no "
+              f"communication: each GPU would run its own chain range (qst_run_desc.chain_offset) and the "
+              f"moment totals would be summed once at the end.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -307,8 +307,8 @@ qst_status qst_chain_state(const qst_problem* p, double* x, double* loglik, doub
  * qst_run_stats.nonfinite_chains counts it), beta [R] in (0, 1], s1 and s2 [R][D*D]
  * (packed, as qst_chain_moments gives them) and n_stored [R]; NULL keeps the
  * handle's own.  Log L and rho of a new x are evaluated at the start of the
- * next qst_run_chains with resume = 1 (a step-free launch of the chain
- * kernel before the run).  The adaptation window's acceptance count is kept,
+ * next qst_run_chains with resume = 1 (a launch of a restore kernel with
+ * the step kernel's launch shape and stage code, before the run).  The adaptation window's acceptance count is kept,
  * so a checkpoint taken at a multiple of M_A restores exactly: resumed, it
  * gives the chains of an uninterrupted run (with the same launch shape).
  * QST_ERR_STATE before any run (a run of 0 steps allocates R chains). */

@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libqst.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # no packed FP32 instructions ("Build")
+    # no packed FP32 instructions: every FP32 operation is issued unpacked
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

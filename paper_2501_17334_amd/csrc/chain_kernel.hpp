@@ -82,7 +82,7 @@ struct ChainArgs {
     int64_t adapt_until;
     int32_t thin;
     int32_t adapt_every;
-    int32_t init;           // 1: draw y^0 (step 0) and evaluate it first; 2: evaluate the stored state
+    int32_t init;           // 1: draw y^0 (step 0) and evaluate it first
                             //    (log L, packed rho) and keep the rest of it
     int32_t poisson;        // 1: Poisson counts: log L -= sum_p W[p] rho_p, W = nd + KD (packed)
     double beta0;
@@ -1308,7 +1308,7 @@ __device__ __forceinline__ double dense_loglik_wg(double* lds_teams, double* red
 // ---------------------------------------------------------------------------
 // the chain tile
 // ---------------------------------------------------------------------------
-template <int Q, int G, int WG, int PATH, int PREC, int PARAM = kParamGamma>
+template <int Q, int G, int WG, int PATH, int PREC, int PARAM = kParamGamma, bool RESTORE = false>
 __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chain0, double* tables, double* lds)
 {
     using Dm = Dims<Q>;
@@ -1468,31 +1468,24 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         return llv;
     };
 
-    // ---- load or initialise the chain state ----
-    if (A.init == 2) {
-        // a state set from outside (checkpoint, restart): y from memory, its
-        // log L and packed rho evaluated here, everything else kept
+    if constexpr (RESTORE) {
+        // a state set from outside (checkpoint, restart): log L and packed
+        // rho of the stored y, with the team shape and code of the step
+        // kernel, so they are the values a run would have carried; nothing
+        // else is touched.  (A kernel of its own: the same branch inside the
+        // step kernel cost it scalar-register spills in the step loop.)
         for (int i = lane; i < d; i += G) ybuf[i] = A.x[c * d + i];
         sync();
-        ll = evaluate();
-#pragma unroll
-        for (int e = 0; e < S::NYL; ++e) {
-            const int i = lane + G * e;
-            y[e] = i < d ? ybuf[i] : 0.0;
+        const double llv = evaluate();
+        if (live) {
+            for (int p = lane; p < D2; p += G) A.rho_cur[c * D2 + p] = rhoP[p];
+            if (lane == 0) A.ll[c] = llv;
         }
-#pragma unroll
-        for (int e = 0; e < S::NPL; ++e) {
-            const int p = packed_slot<Q, G>(lane, e);
-            const bool ok = p < D2;
-            rc[e] = ok ? rhoP[p] : 0.0;
-            s1[e] = ok ? A.s1[c * D2 + p] : 0.0;
-            s2[e] = ok ? A.s2[c * D2 + p] : 0.0;
-        }
-        beta = A.beta[c];
-        acc_w = A.acc_win[c];
-        nst = A.n_stored[c];
-        sync();
-    } else if (A.init) {
+        return;
+    }
+
+    // ---- load or initialise the chain state ----
+    if (A.init) {
         draw_all(0);                     // y^0 ~ N(0, I): Algorithm 2, first line
         __syncthreads();
         ll = evaluate();
@@ -1661,6 +1654,18 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainA
     __syncthreads();
     chain_tile<Q, G, WG, PATH, PREC, PARAM>(A, chain0 + static_cast<int64_t>(blockIdx.x) * (WG / G), lds,
                                             lds + WgTables<Q, PATH>::kDoubles);
+}
+
+// log L and packed rho of restored states (qst_set_chain_state), written to
+// ll and rho_cur; same template arguments as the step kernel they precede.
+template <int Q, int G, int WG, int PATH = kPathKron, int PREC = kPrecF64, int PARAM = kParamGamma>
+__global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains_restore(ChainArgs A, int64_t chain0)
+{
+    extern __shared__ double lds[];
+    wg_tables_init<Q, PATH>(lds, threadIdx.x, WG);
+    __syncthreads();
+    chain_tile<Q, G, WG, PATH, PREC, PARAM, true>(A, chain0 + static_cast<int64_t>(blockIdx.x) * (WG / G), lds,
+                                                  lds + WgTables<Q, PATH>::kDoubles);
 }
 
 // Eq. (likelihood) for n given density matrices (complex, interleaved,

@@ -336,17 +336,24 @@ bool shape_compiled(int Q, Shape sh)
 }
 
 // a.R is one past the last problem-wide chain index, chain0 the first (make_args)
+// restore: the kernel that evaluates restored states instead of the steps
 template <int Q, int G, int WG, int PATH, int PREC, int PARAM = qst::kParamGamma>
-void launch_chains_t(const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
+void launch_chains_t(const qst::ChainArgs& a, int64_t chain0, hipStream_t s, bool restore)
 {
     using S = qst::TeamShape<Q, G, PATH, PARAM>;
     const int64_t teams = WG / G;
     const int64_t blocks = (a.R - chain0 + teams - 1) / teams;
     const size_t lds = (static_cast<size_t>(teams) * S::kLdsChain + qst::WgTables<Q, PATH>::kDoubles) * sizeof(double);
-    allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC, PARAM>), lds);
     if (blocks > 0x7fffffff) fail(QST_ERR_INVALID, "too many chains for one launch");
-    hipLaunchKernelGGL((qst::k_chains<Q, G, WG, PATH, PREC, PARAM>), dim3(static_cast<unsigned>(blocks)), dim3(WG),
-                       lds, s, a, chain0);
+    if (restore) {
+        allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_restore<Q, G, WG, PATH, PREC, PARAM>), lds);
+        hipLaunchKernelGGL((qst::k_chains_restore<Q, G, WG, PATH, PREC, PARAM>), dim3(static_cast<unsigned>(blocks)),
+                           dim3(WG), lds, s, a, chain0);
+    } else {
+        allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains<Q, G, WG, PATH, PREC, PARAM>), lds);
+        hipLaunchKernelGGL((qst::k_chains<Q, G, WG, PATH, PREC, PARAM>), dim3(static_cast<unsigned>(blocks)),
+                           dim3(WG), lds, s, a, chain0);
+    }
     hip_check(hipGetLastError(), "chain kernel launch");
 }
 
@@ -381,13 +388,14 @@ void launch_loglik_t(const double* nd, const uint16_t* mu, const double* ndv, co
 
 // Dirichlet(alpha) weights: the Kronecker route with the default team shape
 // of each qubit count.
-void launch_chains_dirichlet(int Q, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
+void launch_chains_dirichlet(int Q, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s,
+                             bool restore = false)
 {
     using namespace qst;
 #define QST_DIR(q, g, wg)                                                                               \
     if (Q == q)                                                                                         \
-        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamDirichlet>(a, chain0, s) \
-                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamDirichlet>(a, chain0, s);
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamDirichlet>(a, chain0, s, restore) \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamDirichlet>(a, chain0, s, restore);
     QST_DIR(1, 8, 64) QST_DIR(2, 16, 64) QST_DIR(3, 32, 64) QST_DIR(4, 64, 256) QST_DIR(5, 256, 256)
     QST_DIR(6, 512, 512)
 #undef QST_DIR
@@ -396,24 +404,26 @@ void launch_chains_dirichlet(int Q, int prec, const qst::ChainArgs& a, int64_t c
 
 // Algorithm 1 (the Bures draw): the Kronecker route with one fixed team
 // shape per qubit count (one wavefront per chain at 4 qubits).
-void launch_chains_bures(int Q, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
+void launch_chains_bures(int Q, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s,
+                         bool restore = false)
 {
     using namespace qst;
 #define QST_BURES(q, g, wg)                                                                             \
     if (Q == q)                                                                                         \
-        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamBures>(a, chain0, s)     \
-                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamBures>(a, chain0, s);
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamBures>(a, chain0, s, restore)     \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamBures>(a, chain0, s, restore);
     QST_BURES(1, 8, 64) QST_BURES(2, 16, 64) QST_BURES(3, 32, 64) QST_BURES(4, 64, 256)
 #undef QST_BURES
     fail(QST_ERR_UNSUPPORTED, "Algorithm 1 (QST_PARAM_BURES) is built for 1..4 qubits");
 }
 
-void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s)
+void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a, int64_t chain0, hipStream_t s,
+                   bool restore = false)
 {
     using namespace qst;
     if (path == kPathDense) {
 #define QST_DENSE(q, pr) \
-    if (Q == q && prec == pr) return launch_chains_t<q, 64, 1024, kPathDense, pr>(a, chain0, s);
+    if (Q == q && prec == pr) return launch_chains_t<q, 64, 1024, kPathDense, pr>(a, chain0, s, restore);
         QST_DENSE(1, kPrecF64) QST_DENSE(1, kPrecF32) QST_DENSE(1, kPrecBF16x3)
         QST_DENSE(2, kPrecF64) QST_DENSE(2, kPrecF32) QST_DENSE(2, kPrecBF16x3)
         QST_DENSE(3, kPrecF64) QST_DENSE(3, kPrecF32) QST_DENSE(3, kPrecBF16x3)
@@ -423,8 +433,8 @@ void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a,
     }
 #define QST_CASE(q, g, wg)                                                                              \
     if (Q == q && sh.G == g && sh.WG == wg)                                                             \
-        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32>(a, chain0, s)                  \
-                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64>(a, chain0, s);
+        return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32>(a, chain0, s, restore)         \
+                                : launch_chains_t<q, g, wg, kPathKron, kPrecF64>(a, chain0, s, restore);
     QST_CASE(1, 8, 64) QST_CASE(1, 16, 64) QST_CASE(1, 64, 64)
     QST_CASE(2, 16, 64) QST_CASE(2, 32, 64) QST_CASE(2, 64, 64)
     QST_CASE(3, 32, 64) QST_CASE(3, 64, 64)
@@ -887,7 +897,7 @@ qst::ChainArgs make_args(qst_problem* p, const qst_run_desc& r, bool problem_wid
     a.adapt_until = r.adapt_until;
     a.thin = r.thin;
     a.adapt_every = r.adapt_every;
-    a.init = r.resume ? (p->reeval ? 2 : 0) : 1;
+    a.init = r.resume ? 0 : 1;
     a.poisson = p->poisson ? 1 : 0;
     a.beta0 = r.beta0;
     a.adapt_lo = r.adapt_lo;
@@ -1160,7 +1170,8 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
         hipStream_t s = static_cast<hipStream_t>(runs[0].stream);
         for (int i = 0; i < n_problems; ++i) prepare_state(problems[i], runs[i]);
         // states set by qst_set_chain_state: log L and packed rho evaluated by
-        // a step-free launch of the chain kernel, then the run resumes from them
+        // the restore kernel of the same shape and code, then the run resumes
+        // from them
         for (int i = 0; i < n_problems; ++i) {
             qst_problem* p = problems[i];
             if (!p->reeval) continue;
@@ -1173,13 +1184,13 @@ qst_status qst_run_chains(qst_problem* const* problems, int32_t n_problems, cons
                 r0.pair_every = r0.pair_chains = 0;
                 const qst::ChainArgs a0 = make_args(p, r0);
                 if (p->param == QST_PARAM_BURES)
-                    launch_chains_bures(p->Q, static_cast<int>(p->precision), a0, p->chain0, s);
+                    launch_chains_bures(p->Q, static_cast<int>(p->precision), a0, p->chain0, s, true);
                 else if (p->param == QST_PARAM_DIRICHLET)
-                    launch_chains_dirichlet(p->Q, static_cast<int>(p->precision), a0, p->chain0, s);
+                    launch_chains_dirichlet(p->Q, static_cast<int>(p->precision), a0, p->chain0, s, true);
                 else
                     launch_chains(p->Q, current_shape(p->Q),
                                   p->path == QST_PATH_DENSE ? qst::kPathDense : qst::kPathKron,
-                                  static_cast<int>(p->precision), a0, p->chain0, s);
+                                  static_cast<int>(p->precision), a0, p->chain0, s, true);
             }
             p->reeval = false;
         }
