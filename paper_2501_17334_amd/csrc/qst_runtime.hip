@@ -1280,6 +1280,16 @@ qst_status qst_get_launch_shape(int32_t n_qubits, int32_t* team, int32_t* workgr
     });
 }
 
+qst_status qst_get_batch_shape(int32_t n_qubits, int32_t* team, int32_t* workgroup)
+{
+    return guarded([&] {
+        if (n_qubits < 1 || n_qubits > 6) fail(QST_ERR_INVALID, "n_qubits must be in 1..6");
+        if (!team || !workgroup) fail(QST_ERR_INVALID, "NULL output");
+        *team = batch_team(n_qubits);
+        *workgroup = qst::batch_wg(qst::batch_class(n_qubits));
+    });
+}
+
 qst_status qst_list_launch_shapes(int32_t n_qubits, int32_t* teams, int32_t* workgroups, int32_t capacity,
                                   int32_t* count)
 {

@@ -94,6 +94,7 @@ def lib():
         L.qst_acf.argtypes = [vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
         L.qst_set_launch_shape.argtypes = [C.c_int32, C.c_int32, C.c_int32]
         L.qst_get_launch_shape.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.qst_get_batch_shape.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.qst_set_auto_path.argtypes = [C.c_int32, C.c_int, C.c_int]
         L.qst_get_auto_path.argtypes = [C.c_int32, C.c_int, C.POINTER(C.c_int)]
         L.qst_list_launch_shapes.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
@@ -117,7 +118,7 @@ def lib():
         L.qst_version.restype = C.c_char_p
         for f in ("qst_init_problem", "qst_run_chains", "qst_pool_moments", "qst_chain_state", "qst_chain_moments",
                   "qst_set_chain_state", "qst_set_auto_path", "qst_get_auto_path",
-                  "qst_loglik", "qst_acf", "qst_set_launch_shape", "qst_get_launch_shape",
+                  "qst_loglik", "qst_acf", "qst_set_launch_shape", "qst_get_launch_shape", "qst_get_batch_shape",
                   "qst_list_launch_shapes", "qst_mlp_create", "qst_mlp_set_params", "qst_mlp_get_params",
                   "qst_mlp_gradients", "qst_mlp_train_step", "qst_mlp_predict", "qst_mlp_surrogate",
                   "qst_mlp_targets", "qst_gather_rows"):
@@ -492,6 +493,13 @@ def set_launch_shape(n_qubits, team, workgroup):
 def get_launch_shape(n_qubits):
     t, w = C.c_int32(), C.c_int32()
     _check(lib().qst_get_launch_shape(n_qubits, C.byref(t), C.byref(w)))
+    return t.value, w.value
+
+
+def get_batch_shape(n_qubits):
+    """(team, workgroup) of n_qubits tiles inside an uneven batch."""
+    t, w = C.c_int32(), C.c_int32()
+    _check(lib().qst_get_batch_shape(n_qubits, C.byref(t), C.byref(w)))
     return t.value, w.value
 
 

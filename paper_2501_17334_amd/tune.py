@@ -3,7 +3,10 @@
 Shapes: for every compiled (team size G, workgroup WG) of a qubit count it
 runs the same synthetic problem (Haar pure state + 10% white noise, 1024
 shots per setting) for a fixed number of chains and steps, times the launch
-with HIP events, and keeps the fastest shape (qst_set_launch_shape).
+with HIP events, and keeps the fastest shape (qst_set_launch_shape).  Batch
+tiles keep one team per qubit count (qst_get_batch_shape); the table records
+whether it is the tuned one, since a batch problem equals its solo run bit
+for bit only with the same team.
 
 Paths: per qubit count (1..4) and precision (FP64, FP32) it times the chain
 step on the Kronecker route and on the dense MFMA contraction, each with its
@@ -134,8 +137,13 @@ def tune(qubits=(1, 2, 3, 4, 5, 6), out=TABLE, verbose=True, paths=True):
             if best is None or rate > best[1]:
                 best = (shape, rate)
         qst.set_launch_shape(Q, *best[0])
+        bteam = qst.get_batch_shape(Q)[0]
         table[str(Q)] = {"team": best[0][0], "workgroup": best[0][1], "chain_steps_per_s": best[1],
-                         "trials": trials, "chains": chains, "steps": steps}
+                         "trials": trials, "chains": chains, "steps": steps,
+                         "batch_team": bteam, "batch_team_is_tuned_team": bteam == best[0][0]}
+        if verbose and bteam != best[0][0]:
+            print(f"[tune] Q={Q}: batch tiles use team {bteam}, single launches tune to {best[0][0]}; "
+                  f"batch runs then differ from solo runs in summation order", flush=True)
     if paths:
         table["paths"] = tune_paths(tuple(q for q in qubits if q <= 4), verbose)
         table["contraction_states_per_s"] = {}

@@ -66,3 +66,23 @@ def test_binding_refuses_host_and_strided_tensors():
         qst._check_run_buffers(dict(chains=1, llprop=torch.zeros((1, 4), dtype=torch.float64)), None, None)
     qst._dev_tensor(None, ("float64",), "buf")          # absent buffers are allowed
     qst._check_run_buffers(None, None, None)
+
+
+def test_batch_tiles_use_the_tuned_single_problem_teams():
+    """Batch tiles run with a fixed team per qubit count (qst_get_batch_shape);
+    a batch problem equals its solo run with that team, so the committed
+    tuning table must choose the same team for single-problem launches, and
+    the shape must be one the library compiles."""
+    import json
+    with open(os.path.join(ROOT, "paper_2501_17334_amd", "tune_gfx950.json")) as f:
+        tuned = json.load(f)
+    for Q in range(1, 7):
+        team, wg = qst.get_batch_shape(Q)
+        assert wg % team == 0 and wg in (256, 512)
+        assert tuned[str(Q)]["team"] == team, (Q, tuned[str(Q)]["team"], team)
+        teams, wgs = (ctypes.c_int32 * 16)(), (ctypes.c_int32 * 16)()
+        n = ctypes.c_int32()
+        qst._check(qst.lib().qst_list_launch_shapes(Q, teams, wgs, 16, ctypes.byref(n)))
+        assert team in list(teams)[:n.value]
+    with pytest.raises(qst.QstError):
+        qst.get_batch_shape(7)

@@ -15,7 +15,6 @@ from tests.gpu_util import first_near_step
 
 pytestmark = pytest.mark.gpu
 
-BATCH_TEAM = {1: 8, 2: 16, 3: 32, 4: 64, 5: 256, 6: 512}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -43,7 +42,7 @@ def test_batch_equals_solo():
     saved = {q: qst.get_launch_shape(q) for q in range(1, 7)}
     try:
         for q in range(1, 7):
-            qst.set_launch_shape(q, BATCH_TEAM[q], max(64, BATCH_TEAM[q]))
+            qst.set_launch_shape(q, qst.get_batch_shape(q)[0], max(64, qst.get_batch_shape(q)[0]))
         for p, cfg, b, sb in zip(probs, cfgs, batch, st_b):
             print(f"[batch] solo Q={p.n_qubits}", flush=True)
             solo = qst.Problem(p.n_qubits, p.counts)
@@ -74,7 +73,7 @@ def test_mixed_precision_batch_equals_solo():
     saved = {q: qst.get_launch_shape(q) for q in range(1, 7)}
     try:
         for q in range(1, 7):
-            qst.set_launch_shape(q, BATCH_TEAM[q], max(64, BATCH_TEAM[q]))
+            qst.set_launch_shape(q, qst.get_batch_shape(q)[0], max(64, qst.get_batch_shape(q)[0]))
         for p, pr, cfg, b in zip(probs, precs, cfgs, batch):
             print(f"[batch mixed] solo Q={p.n_qubits} {pr}", flush=True)
             solo = qst.Problem(p.n_qubits, p.counts, precision=pr, path="kron")
