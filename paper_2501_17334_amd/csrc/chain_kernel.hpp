@@ -1454,6 +1454,9 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             sync();
             double part = 0.0;
             stage_loglik_f32<Q, G>(pauli32, A.nd, A.mu, A.ndv, A.muv, lane, part);
+            // Poisson counts: minus sum_m lambda_m p_m (FP64, from packed rho),
+            // in the same team reduction
+            if (A.poisson) part -= kInvLn2 * linear_share<Q, G>(A.nd + Dm::KD, rhoP, lane);
             llv = kLn2 * team_sum<G>(part, misc + 4, lane);
         } else {
             stage_pauli<Q, G>(rhoP, pauli, lane);
@@ -1461,10 +1464,13 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             double part_e = 0.0, part_f = 0.0;
             int bad = 0;
             stage_loglik<Q, G>(pauli, A.nd, A.mu, A.ndv, A.muv, tables, lane, part_e, part_f, bad);
+            if (A.poisson) part_f -= linear_share<Q, G>(A.nd + Dm::KD, rhoP, lane);   // as above
             llv = team_loglik<G>(part_e, part_f, bad, misc + 4, lane);
         }
-        if (A.poisson)      // Poisson counts: minus sum_m lambda_m p_m, in FP64 from packed rho
-            llv -= team_sum<G>(linear_share<Q, G>(A.nd + Dm::KD, rhoP, lane), misc + 4, lane);
+        if constexpr (PATH == kPathDense) {
+            if (A.poisson)   // Poisson counts: minus sum_m lambda_m p_m, in FP64 from packed rho
+                llv -= team_sum<G>(linear_share<Q, G>(A.nd + Dm::KD, rhoP, lane), misc + 4, lane);
+        }
         return llv;
     };
 

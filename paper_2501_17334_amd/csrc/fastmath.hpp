@@ -23,6 +23,7 @@ namespace qst {
 
 constexpr int kLogTableSize = 128;   // breakpoints of the table-driven logarithm
 constexpr double kLn2 = 0.693147180559945309417232121458176568;
+constexpr double kInvLn2 = 1.442695040888963407359924681001892137;
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
 // Table entry j: c2 = 2 / (1 + (j + 1/2)/128) (applied to the frexp mantissa
