@@ -34,6 +34,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fastmath.hpp"
 #include "rng.hpp"
 
@@ -463,11 +465,12 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         constexpr int LPC = G / D;          // lanes per column: 2, 4 or 8
         constexpr int RPL = D / LPC;        // rows per lane
         static_assert(LPC >= 2 && LPC <= 8, "column groups must sit inside a DPP row");
-        double V = 0.0;
-#pragma unroll 4
-        for (int j = 0; j < D; ++j) {
-            const double v = vbuf[j];
-            V += v * v;
+        static_assert(D == 32 || D == 64, "one wavefront spans the v_j");
+        // V = sum_j v_j^2 within each wavefront: lane l squares v_(l mod D)
+        double V;
+        {
+            const double v = vbuf[lane & (D - 1)];
+            V = butterfly_sum<D / 2>(v * v);
         }
         {
             const int j = lane / LPC, q = lane % LPC;
@@ -495,19 +498,32 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             const int tile = (lane >> 6) * L::kTilesPerWave + m;
             const int r0 = 16 * (tile / L::kTileDim), c0 = 16 * (tile % L::kTileDim);
             double4_t re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+            // the packed form keeps Re above the diagonal and Im below it, so
+            // a tile off the diagonal needs one of the two products
+            auto gram = [&](auto want_re, auto want_im) {
 #pragma unroll 4
-            for (int s = 0; s < D / 4; ++s) {
-                const int j = 4 * s + kq;
-                const double sj = wt[j];
-                const double ar = ybuf[j * D + r0 + i] * sj;
-                const double ai = ybuf[D2 + j * D + r0 + i] * sj;
-                const double br = ybuf[j * D + c0 + i] * sj;
-                const double bi = ybuf[D2 + j * D + c0 + i] * sj;
-                re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, re, 0, 0, 0);
-                re = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, re, 0, 0, 0);
-                im = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, im, 0, 0, 0);
-                im = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, im, 0, 0, 0);
-            }
+                for (int s = 0; s < D / 4; ++s) {
+                    const int j = 4 * s + kq;
+                    const double sj = wt[j];
+                    const double ar = ybuf[j * D + r0 + i] * sj;
+                    const double ai = ybuf[D2 + j * D + r0 + i] * sj;
+                    const double br = ybuf[j * D + c0 + i] * sj;
+                    const double bi = ybuf[D2 + j * D + c0 + i] * sj;
+                    if constexpr (decltype(want_re)::value) {
+                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, re, 0, 0, 0);
+                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, re, 0, 0, 0);
+                    }
+                    if constexpr (decltype(want_im)::value) {
+                        im = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, im, 0, 0, 0);
+                        im = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, im, 0, 0, 0);
+                    }
+                }
+            };
+            using yes = std::true_type;
+            using no = std::false_type;
+            if (r0 < c0) gram(yes{}, no{});
+            else if (r0 > c0) gram(no{}, yes{});
+            else gram(yes{}, yes{});
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int a = r0 + kq + 4 * r, b = c0 + i;
@@ -525,11 +541,11 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         // column norms |z_j|^2 are butterfly sums over the 16 lanes of its row
         // group and the weights never pass through LDS.
         const int i = lane & 15, kq = lane >> 4;
-        double V = 0.0;
-#pragma unroll 4
-        for (int j = 0; j < D; ++j) {
-            const double v = vbuf[j];
-            V += v * v;
+        // V = sum_j v_j^2 by a butterfly over each row of 16 lanes
+        double V;
+        {
+            const double v = vbuf[i];
+            V = butterfly_sum<8>(v * v);
         }
         double zr[4], zi[4];
 #pragma unroll
@@ -548,18 +564,28 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             zi[t] *= sj;
         }
         typedef double double4_t __attribute__((ext_vector_type(4)));
-        double4_t re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+        // Im rho = Zi Zr^T - Zr Zi^T = X - X^T with X = Zi Zr^T: four products
+        // for X and a transpose through LDS instead of eight for Im rho
+        double4_t re = {0.0, 0.0, 0.0, 0.0}, x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             re = __builtin_amdgcn_mfma_f64_16x16x4f64(zr[t], zr[t], re, 0, 0, 0);
             re = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zi[t], re, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zr[t], im, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f64_16x16x4f64(-zr[t], zi[t], im, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zr[t], x, 0, 0, 0);
         }
+        // result register e of lane l: row l/16 + 4e, column l%16
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rhoP[(kq + 4 * e) * 16 + i] = x[e];
+        team_sync<G>();
+        double xt[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xt[e] = rhoP[i * 16 + kq + 4 * e];   // X at (column, row)
+        team_sync<G>();
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int row = kq + 4 * e, col = i;   // result register e of lane l: row l/16 + 4e
-            const double v = row <= col ? re[e] : -im[e];   // P[a][b] = Im rho_ba = -Im rho_ab below
+            const int row = kq + 4 * e, col = i;
+            // P[a][b] = Im rho_ba = X_ba - X_ab below the diagonal
+            const double v = row <= col ? re[e] : xt[e] - x[e];
             rp[e] = v;
             rhoP[row * 16 + col] = v;
         }
