@@ -1044,13 +1044,13 @@ __device__ __forceinline__ void stage_loglik(const double* pauli, const double* 
     using LS = LikSplit<Q, G>;
     constexpr int D = LS::D, V = LS::V, L = LS::L;
     const LogEntry* tab = reinterpret_cast<const LogEntry*>(tables);
+    // log p with p = val 2^-Q: the table logarithm of val, its exponent less Q
     auto term = [&](double val, double n) {
-        const double p = val * (1.0 / D);
-        const bool pos = p > 0.0;
+        const bool pos = val > 0.0;
         bad |= (n > 0.0 && !pos) ? 1 : 0;
         int ex;
-        const double fr = log_parts(pos ? p : 1.0, tab, ex);
-        part_e = __builtin_fma(n, static_cast<double>(ex), part_e);
+        const double fr = log_parts(pos ? val : 1.0, tab, ex);
+        part_e = __builtin_fma(n, static_cast<double>(ex - Q), part_e);
         part_f = __builtin_fma(n, fr, part_f);
     };
     const int tl = lane & (L - 1);
