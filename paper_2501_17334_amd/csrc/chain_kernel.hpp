@@ -1562,6 +1562,11 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
     // ---- Algorithm 2 ----
     int kr = 0;   // position of the step in its group of kRing steps
     double a = sqrt(1.0 - beta * beta);   // the pCN contraction, recomputed when beta changes
+    // j mod M_A and j mod T, carried from step to step (no 64-bit remainder
+    // in the loop)
+    const int32_t ma = A.adapt_every > 0 ? A.adapt_every : 1;
+    int32_t ja = static_cast<int32_t>((A.step_begin + 1) % ma);
+    int32_t jt = static_cast<int32_t>((A.step_begin + 1) % A.thin);
     for (int64_t t = 0; t < A.n_steps; ++t) {
         const int64_t j = A.step_begin + 1 + t;
         draw(static_cast<uint64_t>(j), kr);
@@ -1604,7 +1609,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             ++acc_w;
             ++nacc;
         }
-        if (A.adapt_every > 0 && j % A.adapt_every == 0) {
+        if (A.adapt_every > 0 && ja == 0) {
             if (A.adapt_until < 0 || j <= A.adapt_until) {
                 const double rate = static_cast<double>(acc_w) / static_cast<double>(A.adapt_every);
                 if (rate > A.adapt_hi) beta = fmin(beta * A.adapt_factor, 1.0);
@@ -1613,7 +1618,7 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             }
             acc_w = 0;
         }
-        if (j > A.burn_in && j % A.thin == 0) {
+        if (j > A.burn_in && jt == 0) {
 #pragma unroll
             for (int e = 0; e < S::NPL; ++e) {
                 s1[e] += rc[e];
@@ -1621,6 +1626,8 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
             }
             ++nst;
         }
+        ja = ja + 1 == ma ? 0 : ja + 1;
+        jt = jt + 1 == A.thin ? 0 : jt + 1;
         if (live && chain < A.trace_chains && lane == 0) {
             const int64_t o = chain * A.n_steps + t;
             if (A.tr_ll) A.tr_ll[o] = llp;
