@@ -547,7 +547,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             const double v = vbuf[i];
             V = butterfly_sum<8>(v * v);
         }
-        double zr[4], zi[4];
+        double zr[4], zi[4], nzt[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int j = 4 * t + kq;
@@ -558,10 +558,20 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             nz += xor_lane<2>(nz);
             nz += xor_lane<4>(nz);
             nz += xor_lane<8>(nz);
-            const double v = vbuf[j];
-            const double sj = fabs(v) * rsqrt_f64(V * nz);   // sqrt(w_j)
-            zr[t] *= sj;
-            zi[t] *= sj;
+            nzt[t] = nz;
+        }
+        // sqrt(w_j) = |v_j| / sqrt(V |z_j|^2) once per column: lane i of a row
+        // computes column 4 (i mod 4) + kq, and lane t of the row hands
+        // column 4 t + kq to the others
+        const int tm = i & 3;
+        const double nzm = tm == 0 ? nzt[0] : (tm == 1 ? nzt[1] : (tm == 2 ? nzt[2] : nzt[3]));
+        const double sm = fabs(vbuf[4 * tm + kq]) * rsqrt_f64(V * nzm);
+        const double sj[4] = {dpp_f64<kDppRowNewBcast0 + 0>(sm), dpp_f64<kDppRowNewBcast0 + 1>(sm),
+                              dpp_f64<kDppRowNewBcast0 + 2>(sm), dpp_f64<kDppRowNewBcast0 + 3>(sm)};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            zr[t] *= sj[t];
+            zi[t] *= sj[t];
         }
         typedef double double4_t __attribute__((ext_vector_type(4)));
         // Im rho = Zi Zr^T - Zr Zi^T = X - X^T with X = Zi Zr^T: four products

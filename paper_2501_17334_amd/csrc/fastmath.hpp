@@ -151,6 +151,7 @@ constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
 constexpr int kDppQuadXor3 = 0x1B;     // quad_perm [3,2,1,0]
 constexpr int kDppRowHalfMirror = 0x141;  // lane i <- lane 7-i within 8 (xor 7)
 constexpr int kDppRowRor8 = 0x128;     // rotate a row of 16 by 8: lane i <- lane (i + 8) mod 16 = i ^ 8
+constexpr int kDppRowNewBcast0 = 0x150;   // + n: every lane of a row of 16 <- lane n of that row
 
 // Exchange across 16- or 32-lane halves with the gfx950 lane-swap
 // instructions: permlane16_swap(v, v) leaves, in each 16-lane row, the

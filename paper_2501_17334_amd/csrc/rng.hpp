@@ -91,10 +91,12 @@ __device__ __forceinline__ void box_muller(uint64_t wa, uint64_t wb, double& n0,
                                            const LogEntry* __restrict__ logtab)
 {
     const double ua = uniform_open(wa);
-    const double ub = uniform_open(wb);
     const double r = sqrt_pos(fmax(-2.0 * fast_log(ua, logtab), 0x1p-52));
+    // 2 u_b = 2 (x - (1 - 2^-53)) for x in [1, 2) from the mantissa bits: one
+    // exact FMA (the difference is exact and doubling it is too)
+    const double xb = __longlong_as_double(static_cast<long long>((wb >> 12) | 0x3FF0000000000000ULL));
     double s, c;
-    sincospi_0_2(2.0 * ub, s, c);
+    sincospi_0_2(__builtin_fma(2.0, xb, -0x1.fffffffffffffp0), s, c);
     n0 = r * c;
     n1 = r * s;
 }
