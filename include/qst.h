@@ -344,7 +344,7 @@ qst_status qst_acf(const double* records, int64_t n_chains, int64_t n_samples, i
                    int32_t l_max, double* out, void* stream);
 
 /* ---------------------------------------------------------------------
- * MLP surrogate of log L for delayed acceptance (spec form 4):
+ * MLP surrogate of log L for delayed acceptance (a production form added to the method):
  * h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2), s = w3 . h2 + b3 (exact erf
  * GELU, Hendrycks & Gimpel 2016), trained by mean squared error and Adam
  * (Kingma & Ba 2015, beta 0.9/0.999, eps 1e-8) with the library's own
