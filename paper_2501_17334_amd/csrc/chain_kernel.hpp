@@ -1695,8 +1695,22 @@ constexpr int chain_min_waves()
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
+// The same capped by what the workgroup's LDS allows on a CU (160 KiB): a
+// shape that fits fewer wavefronts per SIMD than its registers would allow
+// gets the registers of the wavefronts that actually run (fewer spills).
+template <int Q, int G, int WG, int PATH, int PARAM>
+constexpr int chain_waves()
+{
+    using S = TeamShape<Q, G, PATH, PARAM>;
+    constexpr long lds = (static_cast<long>(WG / G) * S::kLdsChain + WgTables<Q, PATH>::kDoubles) * 8;
+    constexpr long wgs = (160L * 1024) / lds;
+    constexpr int w_lds = static_cast<int>((wgs * (WG / 64) + 3) / 4);
+    constexpr int w_reg = chain_min_waves<Q, G>();
+    return w_lds < 1 ? 1 : (w_lds < w_reg ? w_lds : w_reg);
+}
+
 template <int Q, int G, int WG, int PATH = kPathKron, int PREC = kPrecF64, int PARAM = kParamGamma>
-__global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainArgs A, int64_t chain0)
+__global__ __launch_bounds__(WG, (chain_waves<Q, G, WG, PATH, PARAM>())) void k_chains(ChainArgs A, int64_t chain0)
 {
     extern __shared__ double lds[];
     wg_tables_init<Q, PATH>(lds, threadIdx.x, WG);
@@ -1708,7 +1722,8 @@ __global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains(ChainA
 // log L and packed rho of restored states (qst_set_chain_state), written to
 // ll and rho_cur; same template arguments as the step kernel they precede.
 template <int Q, int G, int WG, int PATH = kPathKron, int PREC = kPrecF64, int PARAM = kParamGamma>
-__global__ __launch_bounds__(WG, (chain_min_waves<Q, G>())) void k_chains_restore(ChainArgs A, int64_t chain0)
+__global__ __launch_bounds__(WG, (chain_waves<Q, G, WG, PATH, PARAM>())) void k_chains_restore(ChainArgs A,
+                                                                                     int64_t chain0)
 {
     extern __shared__ double lds[];
     wg_tables_init<Q, PATH>(lds, threadIdx.x, WG);
