@@ -932,14 +932,15 @@ __device__ __forceinline__ void wht_in_lane(T (&v)[V])
 
 // Work split of the Pauli-coefficient transforms: a lane holds V positions
 // a = al + L j (j < V, L = D / V) of generalised diagonal m (task u = m L +
-// al), V = min(2, D^2 / G) so that the tasks still fill the team; the top
-// butterfly stage is then a register add.  (Four positions, with re and im
-// of each in registers, spilled more and ran slower at 4 qubits.)
+// al), V at most D^2 / G so that the tasks still fill the team; the top
+// log2 V butterfly stages are then register adds.  V = 2 up to 4 qubits
+// (four positions, with re and im of each in registers, ran slower there)
+// and 4 from 5 qubits on.
 template <int Q, int G>
 struct PauliSplit {
     static constexpr int D = 1 << Q, D2 = D * D;
     static constexpr int kFill = D2 / G;
-    static constexpr int V = kFill >= 2 ? 2 : 1;
+    static constexpr int V = (Q >= 5 && kFill >= 4) ? 4 : (kFill >= 2 ? 2 : 1);
     static constexpr int L = D / V;
     static constexpr int kLogL = L == 1 ? 0 : L == 2 ? 1 : L == 4 ? 2 : L == 8 ? 3 : L == 16 ? 4 : 5;
     static constexpr int kTasks = D * L;
