@@ -450,7 +450,10 @@ __device__ __forceinline__ void stage_weights(const double* ybuf, const double* 
 // slots): entry (a, b) is sum_j w_j Re(z_aj conj z_bj) for a <= b and
 // sum_j w_j Im(z_bj conj z_aj) for a > b.  Z from ybuf (x layout), the
 // weight parameters v_j from vbuf (x[2D^2 + j], or their Dirichlet form).
-template <int Q, int G>
+// F32 (the mixed-precision Kronecker form, whose likelihood reads rho'
+// rounded to FP32): at 4 qubits the Gram products run on the FP32 matrix
+// pipe, at twice the rate of the FP64 one.
+template <int Q, int G, bool F32 = false, bool RP = true>
 __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf, double* wt, double* rhoP,
                                           double (&rp)[TeamShape<Q, G>::NPL], int lane)
 {
@@ -492,12 +495,14 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         }
         __syncthreads();
         typedef double double4_t __attribute__((ext_vector_type(4)));
+        typedef float float4_t __attribute__((ext_vector_type(4)));
+        using acc_t = std::conditional_t<F32, float4_t, double4_t>;
         const int l = lane & 63, i = l & 15, kq = l >> 4;
 #pragma unroll
         for (int m = 0; m < L::kTilesPerWave; ++m) {
             const int tile = (lane >> 6) * L::kTilesPerWave + m;
             const int r0 = 16 * (tile / L::kTileDim), c0 = 16 * (tile % L::kTileDim);
-            double4_t re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+            acc_t re = {}, im = {};
             // the packed form keeps Re above the diagonal and Im below it, so
             // a tile off the diagonal needs one of the two products
             auto gram = [&](auto want_re, auto want_im) {
@@ -509,13 +514,26 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
                     const double ai = ybuf[D2 + j * D + r0 + i] * sj;
                     const double br = ybuf[j * D + c0 + i] * sj;
                     const double bi = ybuf[D2 + j * D + c0 + i] * sj;
-                    if constexpr (decltype(want_re)::value) {
-                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, re, 0, 0, 0);
-                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, re, 0, 0, 0);
-                    }
-                    if constexpr (decltype(want_im)::value) {
-                        im = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, im, 0, 0, 0);
-                        im = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, im, 0, 0, 0);
+                    if constexpr (F32) {
+                        const float far = static_cast<float>(ar), fai = static_cast<float>(ai);
+                        const float fbr = static_cast<float>(br), fbi = static_cast<float>(bi);
+                        if constexpr (decltype(want_re)::value) {
+                            re = __builtin_amdgcn_mfma_f32_16x16x4f32(far, fbr, re, 0, 0, 0);
+                            re = __builtin_amdgcn_mfma_f32_16x16x4f32(fai, fbi, re, 0, 0, 0);
+                        }
+                        if constexpr (decltype(want_im)::value) {
+                            im = __builtin_amdgcn_mfma_f32_16x16x4f32(fai, fbr, im, 0, 0, 0);
+                            im = __builtin_amdgcn_mfma_f32_16x16x4f32(-far, fbi, im, 0, 0, 0);
+                        }
+                    } else {
+                        if constexpr (decltype(want_re)::value) {
+                            re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, re, 0, 0, 0);
+                            re = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, re, 0, 0, 0);
+                        }
+                        if constexpr (decltype(want_im)::value) {
+                            im = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, im, 0, 0, 0);
+                            im = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, im, 0, 0, 0);
+                        }
                     }
                 }
             };
@@ -524,13 +542,20 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             if (r0 < c0) gram(yes{}, no{});
             else if (r0 > c0) gram(no{}, yes{});
             else gram(yes{}, yes{});
+            // result register r of lane l: row l/16 + 4 r (FP64) or 4 (l/16) + r
+            // (FP32) of the tile, column l%16
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int a = r0 + kq + 4 * r, b = c0 + i;
-                const double v = a <= b ? re[r] : -im[r];
-                rp[4 * m + r] = v;
+                const int a = r0 + (F32 ? 4 * kq + r : kq + 4 * r), b = c0 + i;
+                const double v = a <= b ? static_cast<double>(re[r]) : -static_cast<double>(im[r]);
+                if constexpr (!F32) rp[4 * m + r] = v;
                 rhoP[a * D + b] = v;
             }
+        }
+        if constexpr (F32 && RP) {   // this lane's packed slots, written by other lanes
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < S::NPL; ++e) rp[e] = rhoP[packed_slot<Q, G>(lane, e)];
         }
     } else if constexpr (RhoLayout<Q, G>::kMfma) {
         // rho = Zs Zs^dag with Zs = Z diag(sqrt w): Re rho = Zr Zr^T + Zi Zi^T and
@@ -572,6 +597,38 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         for (int t = 0; t < 4; ++t) {
             zr[t] *= sj[t];
             zi[t] *= sj[t];
+        }
+        if constexpr (F32) {
+            // the same products in FP32; result register e of lane l is row
+            // 4 (l/16) + e, column l%16
+            typedef float float4_t __attribute__((ext_vector_type(4)));
+            float4_t re = {0.0f, 0.0f, 0.0f, 0.0f}, x = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float ar = static_cast<float>(zr[t]), ai = static_cast<float>(zi[t]);
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, ar, re, 0, 0, 0);
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, ai, re, 0, 0, 0);
+                x = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, ar, x, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rhoP[(4 * kq + e) * 16 + i] = static_cast<double>(x[e]);
+            team_sync<G>();
+            double xt[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xt[e] = rhoP[i * 16 + 4 * kq + e];
+            team_sync<G>();
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 4 * kq + e, col = i;
+                rhoP[row * 16 + col] =
+                    row <= col ? static_cast<double>(re[e]) : xt[e] - static_cast<double>(x[e]);
+            }
+            if constexpr (RP) {   // this lane's packed slots, written by other lanes
+                team_sync<G>();
+#pragma unroll
+                for (int e = 0; e < 4; ++e) rp[e] = rhoP[packed_slot<Q, G>(lane, e)];
+            }
+            return;
         }
         typedef double double4_t __attribute__((ext_vector_type(4)));
         // Im rho = Zi Zr^T - Zr Zi^T = X - X^T with X = Zi Zr^T: four products
@@ -629,11 +686,11 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
 
 // The same without the register copy: packed rho' stays in rhoP only, where
 // each lane finds its own slots p = packed_slot(lane, e) again.
-template <int Q, int G>
+template <int Q, int G, bool F32 = false>
 __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf, double* wt, double* rhoP, int lane)
 {
     double unused[TeamShape<Q, G>::NPL];
-    stage_rho<Q, G>(ybuf, vbuf, wt, rhoP, unused, lane);
+    stage_rho<Q, G, F32, false>(ybuf, vbuf, wt, rhoP, unused, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1477,9 +1534,9 @@ __device__ __forceinline__ void chain_tile(const ChainArgs& A, int64_t tile_chai
         } else if constexpr (PARAM == kParamDirichlet) {
             // v in the Pauli region; misc[0] holds the uniform, the sum uses misc[4..]
             stage_dirichlet_v<Q, G>(ybuf, pauli, A.alpha, A.lg_alpha, misc + 4, lane);
-            stage_rho<Q, G>(ybuf, pauli, wt, rhoP, lane);
+            stage_rho<Q, G, PATH == kPathKron && PREC == kPrecF32>(ybuf, pauli, wt, rhoP, lane);
         } else {
-            stage_rho<Q, G>(ybuf, ybuf + 2 * D2, wt, rhoP, lane);
+            stage_rho<Q, G, PATH == kPathKron && PREC == kPrecF32>(ybuf, ybuf + 2 * D2, wt, rhoP, lane);
         }
         sync();
         double llv;
