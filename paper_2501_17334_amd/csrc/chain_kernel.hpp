@@ -539,17 +539,56 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             };
             using yes = std::true_type;
             using no = std::false_type;
-            if (r0 < c0) gram(yes{}, no{});
-            else if (r0 > c0) gram(no{}, yes{});
-            else gram(yes{}, yes{});
             // result register r of lane l: row l/16 + 4 r (FP64) or 4 (l/16) + r
             // (FP32) of the tile, column l%16
+            auto row_of = [&](int r) { return F32 ? 4 * kq + r : kq + 4 * r; };
+            if (r0 != c0) {
+                if (r0 < c0) gram(yes{}, no{});
+                else gram(no{}, yes{});
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int a = r0 + (F32 ? 4 * kq + r : kq + 4 * r), b = c0 + i;
-                const double v = a <= b ? static_cast<double>(re[r]) : -static_cast<double>(im[r]);
-                if constexpr (!F32) rp[4 * m + r] = v;
-                rhoP[a * D + b] = v;
+                for (int r = 0; r < 4; ++r) {
+                    const int a = r0 + row_of(r), b = c0 + i;
+                    const double v = a <= b ? static_cast<double>(re[r]) : -static_cast<double>(im[r]);
+                    if constexpr (!F32) rp[4 * m + r] = v;
+                    rhoP[a * D + b] = v;
+                }
+            } else {
+                // a diagonal tile: Im = X - X^T with X = Zi Zr^T over the tile's
+                // rows (one product instead of two), X transposed through the
+                // tile's own LDS slots, which only this wavefront writes
+                acc_t x = {};
+#pragma unroll 4
+                for (int s = 0; s < D / 4; ++s) {
+                    const int j = 4 * s + kq;
+                    const double sj = wt[j];
+                    const double ar = ybuf[j * D + r0 + i] * sj;
+                    const double ai = ybuf[D2 + j * D + r0 + i] * sj;
+                    if constexpr (F32) {
+                        const float far = static_cast<float>(ar), fai = static_cast<float>(ai);
+                        re = __builtin_amdgcn_mfma_f32_16x16x4f32(far, far, re, 0, 0, 0);
+                        re = __builtin_amdgcn_mfma_f32_16x16x4f32(fai, fai, re, 0, 0, 0);
+                        x = __builtin_amdgcn_mfma_f32_16x16x4f32(fai, far, x, 0, 0, 0);
+                    } else {
+                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ar, re, 0, 0, 0);
+                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, ai, re, 0, 0, 0);
+                        x = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, ar, x, 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) rhoP[(r0 + row_of(r)) * D + c0 + i] = static_cast<double>(x[r]);
+                team_sync<64>();
+                double xt[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xt[r] = rhoP[(r0 + i) * D + c0 + row_of(r)];   // X at (column, row)
+                team_sync<64>();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int a = r0 + row_of(r), b = c0 + i;
+                    // P[a][b] = Im rho_ba = X_ba - X_ab below the diagonal
+                    const double v = a <= b ? static_cast<double>(re[r]) : xt[r] - static_cast<double>(x[r]);
+                    if constexpr (!F32) rp[4 * m + r] = v;
+                    rhoP[a * D + b] = v;
+                }
             }
         }
         if constexpr (F32 && RP) {   // this lane's packed slots, written by other lanes
