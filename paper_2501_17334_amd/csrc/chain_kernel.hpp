@@ -555,7 +555,10 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             } else {
                 // a diagonal tile: Im = X - X^T with X = Zi Zr^T over the tile's
                 // rows (one product instead of two), X transposed through the
-                // tile's own LDS slots, which only this wavefront writes
+                // tile's own LDS slots, which only this wavefront writes.  Re
+                // comes from the same X: with Zp = Zr + Zi, Zp Zp^T =
+                // Re + X + X^T, so Re = Zp Zp^T - X - X^T (two products per
+                // tile instead of three)
                 acc_t x = {};
 #pragma unroll 4
                 for (int s = 0; s < D / 4; ++s) {
@@ -565,12 +568,12 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
                     const double ai = ybuf[D2 + j * D + r0 + i] * sj;
                     if constexpr (F32) {
                         const float far = static_cast<float>(ar), fai = static_cast<float>(ai);
-                        re = __builtin_amdgcn_mfma_f32_16x16x4f32(far, far, re, 0, 0, 0);
-                        re = __builtin_amdgcn_mfma_f32_16x16x4f32(fai, fai, re, 0, 0, 0);
+                        const float fap = far + fai;
+                        re = __builtin_amdgcn_mfma_f32_16x16x4f32(fap, fap, re, 0, 0, 0);
                         x = __builtin_amdgcn_mfma_f32_16x16x4f32(fai, far, x, 0, 0, 0);
                     } else {
-                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ar, re, 0, 0, 0);
-                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, ai, re, 0, 0, 0);
+                        const double ap = ar + ai;
+                        re = __builtin_amdgcn_mfma_f64_16x16x4f64(ap, ap, re, 0, 0, 0);
                         x = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, ar, x, 0, 0, 0);
                     }
                 }
@@ -585,7 +588,8 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
                 for (int r = 0; r < 4; ++r) {
                     const int a = r0 + row_of(r), b = c0 + i;
                     // P[a][b] = Im rho_ba = X_ba - X_ab below the diagonal
-                    const double v = a <= b ? static_cast<double>(re[r]) : xt[r] - static_cast<double>(x[r]);
+                    const double xr = static_cast<double>(x[r]);
+                    const double v = a <= b ? (static_cast<double>(re[r]) - xr) - xt[r] : xt[r] - xr;
                     if constexpr (!F32) rp[4 * m + r] = v;
                     rhoP[a * D + b] = v;
                 }
@@ -598,8 +602,8 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         }
     } else if constexpr (RhoLayout<Q, G>::kMfma) {
         // rho = Zs Zs^dag with Zs = Z diag(sqrt w): Re rho = Zr Zr^T + Zi Zi^T and
-        // Im rho = Zi Zr^T - Zr Zi^T, i.e. two 16x16 real products with K = 32,
-        // eight v_mfma_f64_16x16x4f64 each.  Operand lane l carries
+        // Im rho = Zi Zr^T - Zr Zi^T, 16x16 real products with K = 16, four
+        // v_mfma_f64_16x16x4f64 each.  Operand lane l carries
         // A[l % 16][k0 + l / 16]; for a Gram product the B operand is the same
         // value.  The lane already holds z_ij for its four columns j, so the
         // column norms |z_j|^2 are butterfly sums over the 16 lanes of its row
@@ -641,12 +645,12 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             // the same products in FP32; result register e of lane l is row
             // 4 (l/16) + e, column l%16
             typedef float float4_t __attribute__((ext_vector_type(4)));
-            float4_t re = {0.0f, 0.0f, 0.0f, 0.0f}, x = {0.0f, 0.0f, 0.0f, 0.0f};
+            float4_t g = {0.0f, 0.0f, 0.0f, 0.0f}, x = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const float ar = static_cast<float>(zr[t]), ai = static_cast<float>(zi[t]);
-                re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, ar, re, 0, 0, 0);
-                re = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, ai, re, 0, 0, 0);
+                const float ap = ar + ai;
+                g = __builtin_amdgcn_mfma_f32_16x16x4f32(ap, ap, g, 0, 0, 0);
                 x = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, ar, x, 0, 0, 0);
             }
 #pragma unroll
@@ -659,8 +663,8 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = 4 * kq + e, col = i;
-                rhoP[row * 16 + col] =
-                    row <= col ? static_cast<double>(re[e]) : xt[e] - static_cast<double>(x[e]);
+                const double xe = static_cast<double>(x[e]);
+                rhoP[row * 16 + col] = row <= col ? (static_cast<double>(g[e]) - xe) - xt[e] : xt[e] - xe;
             }
             if constexpr (RP) {   // this lane's packed slots, written by other lanes
                 team_sync<G>();
@@ -671,12 +675,15 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         }
         typedef double double4_t __attribute__((ext_vector_type(4)));
         // Im rho = Zi Zr^T - Zr Zi^T = X - X^T with X = Zi Zr^T: four products
-        // for X and a transpose through LDS instead of eight for Im rho
-        double4_t re = {0.0, 0.0, 0.0, 0.0}, x = {0.0, 0.0, 0.0, 0.0};
+        // for X and a transpose through LDS instead of eight for Im rho.  Re
+        // rho from the same X: Zp Zp^T = Re + X + X^T, so
+        // four products for Zp Zp^T (Zp = Zr + Zi) instead of eight for
+        // Zr Zr^T + Zi Zi^T
+        double4_t g = {0.0, 0.0, 0.0, 0.0}, x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zr[t], zr[t], re, 0, 0, 0);
-            re = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zi[t], re, 0, 0, 0);
+            const double zp = zr[t] + zi[t];
+            g = __builtin_amdgcn_mfma_f64_16x16x4f64(zp, zp, g, 0, 0, 0);
             x = __builtin_amdgcn_mfma_f64_16x16x4f64(zi[t], zr[t], x, 0, 0, 0);
         }
         // result register e of lane l: row l/16 + 4e, column l%16
@@ -691,7 +698,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         for (int e = 0; e < 4; ++e) {
             const int row = kq + 4 * e, col = i;
             // P[a][b] = Im rho_ba = X_ba - X_ab below the diagonal
-            const double v = row <= col ? re[e] : xt[e] - x[e];
+            const double v = row <= col ? (g[e] - x[e]) - xt[e] : xt[e] - x[e];
             rp[e] = v;
             rhoP[row * 16 + col] = v;
         }
