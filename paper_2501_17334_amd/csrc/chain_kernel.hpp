@@ -476,11 +476,18 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             V = butterfly_sum<D / 2>(v * v);
         }
         {
+            // lane (j, q) sums rows q RPL .. q RPL + RPL - 1 of column j.  At
+            // 6 qubits it starts at row offset j mod RPL, so that the
+            // wavefront's eight columns read different LDS banks at every r
+            // (unrotated, all of them read the same four: 6 qubits 163 -> 157
+            // ns per chain-step); at 5 qubits the rotation's address
+            // arithmetic cost more than its fewer conflicts saved
             const int j = lane / LPC, q = lane % LPC;
+            const int rot = Q >= 6 ? j : 0;
             double nz = 0.0;
 #pragma unroll 4
             for (int r = 0; r < RPL; ++r) {
-                const int i = q * RPL + r;
+                const int i = q * RPL + ((r + rot) & (RPL - 1));
                 const double re = ybuf[j * D + i];
                 const double im = ybuf[D2 + j * D + i];
                 nz += re * re + im * im;
