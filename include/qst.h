@@ -264,8 +264,8 @@ qst_status qst_set_auto_path(int32_t n_qubits, qst_precision precision, qst_path
 qst_status qst_get_auto_path(int32_t n_qubits, qst_precision precision, qst_path* path);
 qst_status qst_get_launch_shape(int32_t n_qubits, int32_t* team, int32_t* workgroup);
 /* The launch shape of n_qubits tiles inside an uneven batch (fixed per
- * qubit count: one team per tile row of a 512-thread workgroup at 6 qubits,
- * 256-thread workgroups otherwise).  A batch problem gives the chains of its
+ * qubit count: one 1024-thread team per workgroup at 6 qubits, 256-thread
+ * workgroups otherwise).  A batch problem gives the chains of its
  * single-problem run with this shape bit for bit. */
 qst_status qst_get_batch_shape(int32_t n_qubits, int32_t* team, int32_t* workgroup);
 /* The compiled shapes for n_qubits: up to `capacity` (team, workgroup) pairs

@@ -7,13 +7,13 @@
 // code as a single-problem launch, on its own problem's buffers, so a
 // problem's results do not depend on the batch around it.
 //
-// A launch's register and LDS allocation is that of its largest tile.  The
-// 6-qubit tiles need 256 VGPRs and about 150 KB of LDS, which leaves room for
-// one 512-thread workgroup per CU (two wavefronts per SIMD); tiles of up to 5
-// qubits fit in 128 VGPRs, i.e. twice the resident wavefronts.  So the batch
-// runs as one launch per qubit count and precision present, back to back on
-// the stream, largest qubit count first: k_chains_batch<Q, precision>, with
-// 512-thread workgroups for the 6-qubit tiles and 256 otherwise.
+// A launch's register and LDS allocation is that of its largest tile.  A
+// 6-qubit tile needs about 150 KB of LDS, which leaves room for one
+// workgroup per CU: its 1024-thread team fills it (four wavefronts per SIMD
+// at 128 VGPRs), while the smaller tiles would lose most of their resident
+// workgroups in such a launch.  So the batch runs as one launch per qubit
+// count and precision present: k_chains_batch<Q, precision>, with
+// 1024-thread workgroups for the 6-qubit tiles and 256 otherwise.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,12 +23,12 @@
 
 namespace qst {
 
-// Launch classes: one per qubit count.  Workgroup size of each class: 512
-// threads for the 6-qubit tiles (one 512-thread team), 256 otherwise, so that
-// a 5-qubit tile is one 256-thread team with barriers of its own, as in its
-// single-problem launch.
+// Launch classes: one per qubit count.  Workgroup size of each class: 1024
+// threads for the 6-qubit tiles (one 1024-thread team), 256 otherwise, so
+// that a 5-qubit tile is one 256-thread team with barriers of its own, as in
+// its single-problem launch.
 constexpr int batch_class(int q) { return q; }
-constexpr int batch_wg(int qmax) { return qmax == 6 ? 512 : 256; }
+constexpr int batch_wg(int qmax) { return qmax == 6 ? 1024 : 256; }
 
 struct BatchItem {
     int32_t problem;   // index into the ChainArgs array
@@ -39,7 +39,7 @@ struct BatchItem {
 };
 
 struct BatchArgs {
-    const ChainArgs* problems;
+    const ChainArgs* __restrict__ problems;   // read only
     const BatchItem* items;
     int32_t n_items;
     int32_t* counter;   // next tile to take; zero at launch
@@ -48,7 +48,7 @@ struct BatchArgs {
 // Team size of each qubit count inside a batch launch.
 template <int Q>
 struct BatchTeam {
-    static constexpr int G = Q == 1 ? 8 : Q == 2 ? 16 : Q == 3 ? 32 : Q == 4 ? 64 : Q == 5 ? 256 : 512;
+    static constexpr int G = Q == 1 ? 8 : Q == 2 ? 16 : Q == 3 ? 32 : Q == 4 ? 64 : Q == 5 ? 256 : 1024;
 };
 
 template <int Q>
@@ -91,10 +91,10 @@ __device__ __forceinline__ void batch_tile(const ChainArgs& A, int64_t chain0)
                                                               batch_lds + WgTables<Q>::kDoubles);
 }
 
-// Wavefronts per SIMD the launch is compiled for: 4 (128 VGPRs) for tiles of
-// up to 5 qubits, 2 (256 VGPRs) for 6-qubit tiles.
+// Wavefronts per SIMD the launch is compiled for: 4 (128 VGPRs) for every
+// class (a 6-qubit workgroup alone brings four).
 template <int QMAX>
-constexpr int batch_waves_per_simd() { return QMAX == 6 ? 2 : 4; }
+constexpr int batch_waves_per_simd() { return 4; }
 
 // One launch per (qubit count, precision), inlining exactly one chain step.
 // The host sorts every tile into the launch of its class; a tile of another
@@ -111,8 +111,16 @@ __global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void 
         __syncthreads();
         if (it >= B.n_items) break;
         const BatchItem I = B.items[it];
-        const ChainArgs A = B.problems[I.problem];
-        if (I.q == QMAX && I.prec == PREC) batch_tile<QMAX, PREC>(A, I.chain0);
+        if constexpr (QMAX == 6 && PREC == kPrecF64) {
+            // the tile's arguments read where they lie (scalar loads on use):
+            // a copy held across the tile cost this class 340 bytes of
+            // register spills per lane instead of 244 and 5 % of its time;
+            // the other classes keep the copy, which is faster for them
+            if (I.q == QMAX && I.prec == PREC) batch_tile<QMAX, PREC>(B.problems[I.problem], I.chain0);
+        } else {
+            const ChainArgs A = B.problems[I.problem];
+            if (I.q == QMAX && I.prec == PREC) batch_tile<QMAX, PREC>(A, I.chain0);
+        }
         __syncthreads();
     }
 }

@@ -465,9 +465,9 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         // lanes share a column, sum |z_ij|^2 over their rows and combine by
         // butterflies; sqrt(w_j) goes to LDS for the operand loads.
         using L = RhoLayout<Q, G>;
-        constexpr int LPC = G / D;          // lanes per column: 2, 4 or 8
+        constexpr int LPC = G / D;          // lanes per column: 2, 4, 8 or 16
         constexpr int RPL = D / LPC;        // rows per lane
-        static_assert(LPC >= 2 && LPC <= 8, "column groups must sit inside a DPP row");
+        static_assert(LPC >= 2 && LPC <= 16, "column groups must sit inside a DPP row");
         static_assert(D == 32 || D == 64, "one wavefront spans the v_j");
         // V = sum_j v_j^2 within each wavefront: lane l squares v_(l mod D)
         double V;
@@ -477,11 +477,12 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
         }
         {
             // lane (j, q) sums rows q RPL .. q RPL + RPL - 1 of column j.  At
-            // 6 qubits it starts at row offset j mod RPL, so that the
-            // wavefront's eight columns read different LDS banks at every r
-            // (unrotated, all of them read the same four: 6 qubits 163 -> 157
-            // ns per chain-step); at 5 qubits the rotation's address
-            // arithmetic cost more than its fewer conflicts saved
+            // 6 qubits it starts at row offset j mod RPL, so that the columns
+            // of a wavefront (eight in a 512-thread team, four in a 1024-thread
+            // one) read different LDS banks at every r (unrotated, all of them
+            // read the same bank pairs: 6 qubits 163 -> 157 ns per
+            // chain-step); at 5 qubits the rotation's address arithmetic cost
+            // more than its fewer conflicts saved
             const int j = lane / LPC, q = lane % LPC;
             const int rot = Q >= 6 ? j : 0;
             double nz = 0.0;
@@ -495,6 +496,7 @@ __device__ __forceinline__ void stage_rho(const double* ybuf, const double* vbuf
             nz += xor_lane<1>(nz);
             if constexpr (LPC >= 4) nz += xor_lane<2>(nz);
             if constexpr (LPC >= 8) nz += xor_lane<4>(nz);
+            if constexpr (LPC >= 16) nz += xor_lane<8>(nz);
             if (q == 0) {
                 const double v = vbuf[j];
                 wt[j] = sqrt((v * v / V) / nz);

@@ -310,12 +310,12 @@ constexpr Shape kShapes[7][5] = {
     {{32, 64}, {64, 64}},
     {{64, 64}, {64, 256}},
     {{64, 64}, {128, 128}, {256, 256}, {512, 512}},
-    {{256, 256}, {512, 512}},
+    {{256, 256}, {512, 512}, {1024, 1024}},
 };
 
 // Current choice per qubit count (set by qst_set_launch_shape, e.g. from the
 // autotuner's table).
-Shape g_shape[7] = {{0, 0}, {8, 64}, {16, 64}, {32, 64}, {64, 256}, {256, 256}, {512, 512}};
+Shape g_shape[7] = {{0, 0}, {8, 64}, {16, 64}, {32, 64}, {64, 256}, {256, 256}, {1024, 1024}};
 
 Shape current_shape(int Q) { return g_shape[Q]; }
 
@@ -397,7 +397,7 @@ void launch_chains_dirichlet(int Q, int prec, const qst::ChainArgs& a, int64_t c
         return prec == kPrecF32 ? launch_chains_t<q, g, wg, kPathKron, kPrecF32, kParamDirichlet>(a, chain0, s, restore) \
                                 : launch_chains_t<q, g, wg, kPathKron, kPrecF64, kParamDirichlet>(a, chain0, s, restore);
     QST_DIR(1, 8, 64) QST_DIR(2, 16, 64) QST_DIR(3, 32, 64) QST_DIR(4, 64, 256) QST_DIR(5, 256, 256)
-    QST_DIR(6, 512, 512)
+    QST_DIR(6, 1024, 1024)
 #undef QST_DIR
     fail(QST_ERR_INVALID, "n_qubits must be in 1..6");
 }
@@ -440,7 +440,7 @@ void launch_chains(int Q, Shape sh, int path, int prec, const qst::ChainArgs& a,
     QST_CASE(3, 32, 64) QST_CASE(3, 64, 64)
     QST_CASE(4, 64, 64) QST_CASE(4, 64, 256)
     QST_CASE(5, 64, 64) QST_CASE(5, 128, 128) QST_CASE(5, 256, 256) QST_CASE(5, 512, 512)
-    QST_CASE(6, 256, 256) QST_CASE(6, 512, 512)
+    QST_CASE(6, 256, 256) QST_CASE(6, 512, 512) QST_CASE(6, 1024, 1024)
 #undef QST_CASE
     fail(QST_ERR_UNSUPPORTED, "no chain kernel for Q=" + std::to_string(Q) + " G=" + std::to_string(sh.G));
 }

@@ -29,7 +29,7 @@ from . import qst, synth
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_gfx950.json")
 
 # chains x steps timed per qubit count (enough work to fill the GPU)
-WORK = {1: (65536, 400), 2: (65536, 300), 3: (65536, 100), 4: (32768, 60), 5: (4096, 20), 6: (1024, 4)}
+WORK = {1: (65536, 400), 2: (65536, 300), 3: (65536, 100), 4: (32768, 60), 5: (4096, 20), 6: (4096, 20)}
 
 
 def _problem(Q):

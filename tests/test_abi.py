@@ -78,7 +78,7 @@ def test_batch_tiles_use_the_tuned_single_problem_teams():
         tuned = json.load(f)
     for Q in range(1, 7):
         team, wg = qst.get_batch_shape(Q)
-        assert wg % team == 0 and wg in (256, 512)
+        assert wg % team == 0 and wg in (256, 1024)
         assert tuned[str(Q)]["team"] == team, (Q, tuned[str(Q)]["team"], team)
         teams, wgs = (ctypes.c_int32 * 16)(), (ctypes.c_int32 * 16)()
         n = ctypes.c_int32()
