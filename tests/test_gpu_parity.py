@@ -128,6 +128,23 @@ def test_q6_lockstep():
     _compare_lockstep(6, p.counts, 3, 3, p.seed, 0.01, 0, trace=3)
 
 
+@pytest.mark.parametrize("Q", [1, 2, 3, 4, 5, 6])
+def test_every_compiled_launch_shape_matches_oracle(Q):
+    """Each compiled (team, workgroup) of a qubit count, not only the tuned
+    one, in lockstep with the oracle (short runs; chain counts that leave a
+    ragged last workgroup)."""
+    p = _problem_for(Q)
+    R, T = {1: (19, 40), 2: (13, 30), 3: (7, 20), 4: (5, 8), 5: (3, 4), 6: (2, 2)}[Q]
+    saved = qst.get_launch_shape(Q)
+    try:
+        for shape in qst.list_launch_shapes(Q):
+            print(f"[shape] Q={Q} team={shape[0]} workgroup={shape[1]}", flush=True)
+            qst.set_launch_shape(Q, *shape)
+            _compare_lockstep(Q, p.counts, R, T, p.seed + 3, 0.02, 0, trace=R)
+    finally:
+        qst.set_launch_shape(Q, *saved)
+
+
 def test_resume_is_bitwise():
     p = synth.make_problem("c2")
     kw = dict(n_chains=64, seed=9, beta0=0.05, adapt_every=50, thin=2, burn_in=20)
