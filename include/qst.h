@@ -236,10 +236,11 @@ qst_status qst_init_problem(const qst_problem_desc* desc, qst_problem** out);
 /* Step 5 / Algorithm 2 on every problem of the batch.  A single problem runs
  * in one persistent kernel launch.  A batch of several handles is the
  * uneven-batch form: problems of 1..6 qubits with any chain counts are cut
- * into workgroup tiles, ordered largest-cost first, and taken from a device
- * work counter by resident workgroups, in one persistent launch per qubit
- * count and precision (a launch's registers and LDS are sized for its
- * tiles); each problem's results are bit-identical to running
+ * into workgroup tiles, ordered largest-cost first, and run in one launch
+ * per qubit count and precision (a launch's registers and LDS are sized for
+ * its tiles): resident workgroups take the tiles from a device work counter,
+ * except at 6 qubits, where a grid of one workgroup per tile runs them in
+ * that order; each problem's results are bit-identical to running
  * it alone with the same team size (qst_set_launch_shape), and equal up to
  * summation order otherwise.  Batches need the Kronecker path, FP64 or FP32
  * per problem (QST_ERR_UNSUPPORTED otherwise), distinct handles on one

@@ -1,19 +1,21 @@
 // Uneven batches: chains of many problems (1 to 6 qubits, any chain count,
-// FP64 or the FP32 Kronecker form per problem) in one persistent launch per
-// launch class.  The host cuts every problem into workgroup tiles (WG / G_Q
-// chains each, G_Q the team size of that qubit count), orders the tiles by
-// estimated cost, largest first, and the resident workgroups take tiles from a
-// global counter until the list is exhausted.  A tile runs the same chain_tile
-// code as a single-problem launch, on its own problem's buffers, so a
-// problem's results do not depend on the batch around it.
+// FP64 or the FP32 Kronecker form per problem) in one launch per launch
+// class.  The host cuts every problem into workgroup tiles (WG / G_Q chains
+// each, G_Q the team size of that qubit count) and orders the tiles by
+// estimated cost, largest first; in a persistent launch the resident
+// workgroups take tiles from a global counter until the list is exhausted,
+// and the 6-qubit class runs as a plain grid of one workgroup per tile in that
+// order.  A tile runs the same chain_tile code as a single-problem launch, on
+// its own problem's buffers, so a problem's results do not depend on the
+// batch around it.
 //
 // A launch's register and LDS allocation is that of its largest tile.  A
 // 6-qubit tile needs about 150 KB of LDS, which leaves room for one
 // workgroup per CU: its 1024-thread team fills it (four wavefronts per SIMD
 // at 128 VGPRs), while the smaller tiles would lose most of their resident
 // workgroups in such a launch.  So the batch runs as one launch per qubit
-// count and precision present: k_chains_batch<Q, precision>, with
-// 1024-thread workgroups for the 6-qubit tiles and 256 otherwise.
+// count and precision present: k_chains_batch<Q, precision> with 256-thread
+// workgroups up to 5 qubits, k_chains_batch_grid<6, precision> with 1024.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,7 +41,7 @@ struct BatchItem {
 };
 
 struct BatchArgs {
-    const ChainArgs* __restrict__ problems;   // read only
+    const ChainArgs* problems;
     const BatchItem* items;
     int32_t n_items;
     int32_t* counter;   // next tile to take; zero at launch
@@ -111,18 +113,23 @@ __global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void 
         __syncthreads();
         if (it >= B.n_items) break;
         const BatchItem I = B.items[it];
-        if constexpr (QMAX == 6 && PREC == kPrecF64) {
-            // the tile's arguments read where they lie (scalar loads on use):
-            // a copy held across the tile cost this class 340 bytes of
-            // register spills per lane instead of 244 and 5 % of its time;
-            // the other classes keep the copy, which is faster for them
-            if (I.q == QMAX && I.prec == PREC) batch_tile<QMAX, PREC>(B.problems[I.problem], I.chain0);
-        } else {
-            const ChainArgs A = B.problems[I.problem];
-            if (I.q == QMAX && I.prec == PREC) batch_tile<QMAX, PREC>(A, I.chain0);
-        }
+        const ChainArgs A = B.problems[I.problem];
+        if (I.q == QMAX && I.prec == PREC) batch_tile<QMAX, PREC>(A, I.chain0);
         __syncthreads();
     }
+}
+
+// The 6-qubit class as a plain grid, one workgroup per tile in the list's
+// largest-first order: with one workgroup per CU and tiles of milliseconds,
+// the work queue gains nothing there, and its loop around the tile cost the
+// tile's registers (300 and 244 bytes of spills per lane in FP64 and FP32,
+// 180 and 148 without it, against 172 and 140 in the single-problem kernel).
+template <int QMAX, int PREC>
+__global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void k_chains_batch_grid(BatchArgs B)
+{
+    const BatchItem I = B.items[blockIdx.x];
+    const ChainArgs A = B.problems[I.problem];
+    if (I.q == QMAX && I.prec == PREC) batch_tile<QMAX, PREC>(A, I.chain0);
 }
 
 __global__ void k_zero_counter(int32_t* c) { c[0] = 0; }

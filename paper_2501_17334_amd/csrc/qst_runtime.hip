@@ -1023,6 +1023,14 @@ void launch_batch_class(const qst::BatchItem* items, size_t n, size_t lds, const
                         int32_t* counter, int n_cu, hipStream_t s)
 {
     if (n == 0) return;
+    qst::BatchArgs b{dargs, items, static_cast<int32_t>(n), counter};
+    if constexpr (QMAX == 6) {   // one workgroup per tile (batch_kernel.hpp)
+        allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_batch_grid<QMAX, PREC>), lds);
+        hipLaunchKernelGGL((qst::k_chains_batch_grid<QMAX, PREC>), dim3(static_cast<unsigned>(n)),
+                           dim3(qst::batch_wg(QMAX)), lds, s, b);
+        hip_check(hipGetLastError(), "batch kernel launch");
+        return;
+    }
     allow_dynamic_lds(reinterpret_cast<const void*>(&qst::k_chains_batch<QMAX, PREC>), lds);
     int per_cu = 0;
     hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, qst::k_chains_batch<QMAX, PREC>,
@@ -1030,7 +1038,6 @@ void launch_batch_class(const qst::BatchItem* items, size_t n, size_t lds, const
               "occupancy");
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(n),
                                                                  static_cast<int64_t>(n_cu) * std::max(per_cu, 1)));
-    qst::BatchArgs b{dargs, items, static_cast<int32_t>(n), counter};
     hipLaunchKernelGGL((qst::k_chains_batch<QMAX, PREC>), dim3(static_cast<unsigned>(grid)),
                        dim3(qst::batch_wg(QMAX)), lds, s, b);
     hip_check(hipGetLastError(), "batch kernel launch");
