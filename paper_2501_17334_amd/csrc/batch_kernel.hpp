@@ -122,7 +122,7 @@ __global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void 
 // The 6-qubit class as a plain grid, one workgroup per tile in the list's
 // largest-first order: with one workgroup per CU and tiles of milliseconds,
 // the work queue gains nothing there, and its loop around the tile cost the
-// tile's registers (300 and 244 bytes of spills per lane in FP64 and FP32,
+// tile's registers (340 and 300 bytes of spills per lane in FP64 and FP32,
 // 180 and 148 without it, against 172 and 140 in the single-problem kernel).
 template <int QMAX, int PREC>
 __global__ __launch_bounds__(batch_wg(QMAX), batch_waves_per_simd<QMAX>()) void k_chains_batch_grid(BatchArgs B)
