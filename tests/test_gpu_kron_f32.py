@@ -89,10 +89,11 @@ def _current_ll(ll0, llprop, accept, k):
     return cur
 
 
-@pytest.mark.parametrize("Q", [2, 4, 5])
+@pytest.mark.parametrize("Q", [1, 2, 3, 4, 5, 6])
 def test_f32_chains_against_oracle(Q):
     prob = _problem_for(Q)
-    R, T, beta0 = {2: (48, 300, 0.05), 4: (32, 80, 0.02), 5: (8, 12, 0.01)}[Q]
+    R, T, beta0 = {1: (40, 400, 0.1), 2: (48, 300, 0.05), 3: (24, 150, 0.03), 4: (32, 80, 0.02),
+                   5: (8, 12, 0.01), 6: (2, 3, 0.01)}[Q]
     print(f"[kron f32 chains] Q={Q} R={R} T={T}", flush=True)
     P = qst.Problem(Q, prob.counts, precision="fp32", path="kron")
     g = gpu_run(Q, prob.counts, n_chains=R, n_steps=T, seed=prob.seed, beta0=beta0, adapt_every=0, trace=R,
