@@ -2,7 +2,7 @@
 Hilferty start, series / continued fraction) against the oracle's
 bisection: chains in lockstep with per-step log L within 1e-10 relative,
 the packed rho of every final state within 1e-12 of the oracle's rho(x),
-on 2, 4 and 5 qubits and alpha from 0.3 to 2; refusals."""
+on 1 to 6 qubits and alpha from 0.3 to 2; refusals."""
 import numpy as np
 import pytest
 import torch
@@ -20,10 +20,13 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("Q,alpha", [(2, 0.3), (2, 2.0), (4, 1.0), (4, 0.5), (5, 1.7)])
+@pytest.mark.parametrize("Q,alpha", [(1, 0.8), (2, 0.3), (2, 2.0), (3, 1.3), (4, 1.0), (4, 0.5), (5, 1.7), (6, 0.7)])
 def test_dirichlet_chains_match_oracle(Q, alpha):
-    prob = {2: synth.make_problem("c2"), 4: synth.make_problem("c3"), 5: synth.make_problem("c4")}[Q]
-    R, T, beta0 = {2: (24, 150, 0.05), 4: (8, 50, 0.02), 5: (4, 8, 0.01)}[Q]
+    prob = {1: synth.make_problem("c1"), 2: synth.make_problem("c2"), 3: synth.make_problem("w_3"),
+            4: synth.make_problem("c3"), 5: synth.make_problem("c4"),
+            6: next(p for p in synth.mixed_batch(64) if p.n_qubits == 6)}[Q]
+    R, T, beta0 = {1: (32, 200, 0.1), 2: (24, 150, 0.05), 3: (16, 80, 0.03), 4: (8, 50, 0.02), 5: (4, 8, 0.01),
+                   6: (2, 3, 0.01)}[Q]
     D = 2 ** Q
     print(f"[dirichlet] Q={Q} alpha={alpha} R={R} T={T}", flush=True)
     P = qst.Problem(Q, prob.counts, param="dirichlet", alpha=alpha)
