@@ -93,8 +93,15 @@ def test_bures_fp32_form():
     bar = 2e-5 * prob.counts.sum()
     for r in range(R):
         diff = np.nonzero(o["trace_accept"][r] != g["accept"][r])[0]
-        s = min((diff[0] if diff.size else T) + 1, T)
+        k = diff[0] if diff.size else T
+        s = min(k + 1, T)
         assert np.all(np.abs(o["trace_llprop"][r, :s] - g["llprop"][r, :s]) <= bar), r
+        if k < T:   # a decision may part only inside the error band of both log L
+            cur = ll0[r]
+            for t in range(k):
+                if o["trace_accept"][r, t]:
+                    cur = o["trace_llprop"][r, t]
+            assert abs(o["trace_logu"][r, k] - (o["trace_llprop"][r, k] - cur)) <= 2.0 * bar, (r, k)
 
 
 def test_bures_fullsize_sampled_chains():
