@@ -28,7 +28,7 @@ def _cfg(prob, R, T, resume=False):
                          resume=resume)
 
 
-@pytest.mark.parametrize("name,R", [("c2", 200), ("c3", 96), ("c4", 8)])
+@pytest.mark.parametrize("name,R", [("c1", 64), ("c2", 200), ("c3", 96), ("c4", 8), ("c5", 3)])
 def test_checkpoint_restore_into_a_fresh_handle(name, R):
     prob = synth.make_problem(name)
     Q = prob.n_qubits

@@ -19,7 +19,8 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("name,R,T,k", [("c2", 300, 400, 137), ("c3", 96, 60, 65), ("c4", 12, 10, 9)])
+@pytest.mark.parametrize("name,R,T,k", [("c1", 64, 200, 23), ("c2", 300, 400, 137), ("c3", 96, 60, 65),
+                                         ("c4", 12, 10, 9), ("c5", 5, 4, 3)])
 def test_tail_of_a_run_alone(name, R, T, k):
     prob = synth.make_problem(name)
     Q = prob.n_qubits
