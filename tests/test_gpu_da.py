@@ -32,9 +32,20 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
+@pytest.fixture(autouse=True)
+def _restore_launch_shapes():
+    # the tests run plain chains with the delayed-acceptance kernels' team
+    # sizes; later tests get the tuned shapes back
+    saved = {q: qst.get_launch_shape(q) for q in range(1, 7)}
+    yield
+    for q, sh in saved.items():
+        qst.set_launch_shape(q, *sh)
+
+
 def _problem(Q):
-    return {1: synth.make_problem("c1"), 2: synth.make_problem("c2"), 4: synth.make_problem("c3"),
-            5: synth.make_problem("c4")}[Q]
+    return {1: synth.make_problem("c1"), 2: synth.make_problem("c2"), 3: synth.make_problem("w_3"),
+            4: synth.make_problem("c3"), 5: synth.make_problem("c4"),
+            6: next(p for p in synth.mixed_batch(64) if p.n_qubits == 6)}[Q]
 
 
 def _run(P, cfg, surrogate=None, trace=0):
@@ -52,11 +63,11 @@ def _run(P, cfg, surrogate=None, trace=0):
     return out
 
 
-@pytest.mark.parametrize("Q", [1, 2, 4, 5])
+@pytest.mark.parametrize("Q", [1, 2, 3, 4, 5, 6])
 def test_constant_surrogate_equals_plain(Q):
     print(f"[da const] Q={Q}", flush=True)
     prob = _problem(Q)
-    R, T = {1: (64, 300), 2: (48, 200), 4: (16, 60), 5: (4, 8)}[Q]
+    R, T = {1: (64, 300), 2: (48, 200), 3: (24, 100), 4: (16, 60), 5: (4, 8), 6: (2, 3)}[Q]
     qst.set_launch_shape(Q, *DA_SHAPE[Q])
     A = qst.Problem(Q, prob.counts)
     B = qst.Problem(Q, prob.counts)
