@@ -145,6 +145,32 @@ def test_every_compiled_launch_shape_matches_oracle(Q):
         qst.set_launch_shape(Q, *saved)
 
 
+@pytest.mark.parametrize("Q", [2, 4])
+def test_independence_proposals_at_beta_one(Q):
+    """beta = 1, the degenerate end of pCN: y' = eta, a fresh prior draw that
+    ignores the current state (adaptation off, so beta stays 1)."""
+    p = _problem_for(Q)
+    R, T = {2: (32, 200), 4: (8, 30)}[Q]
+    g, ch, n = _compare_lockstep(Q, p.counts, R, T, p.seed + 11, 1.0, 0, trace=R)
+    assert np.all(g["problem"].state()[2] == 1.0)
+
+
+def test_runs_that_store_no_sample():
+    """burn-in or thinning that excludes every step: no chain stores a sample
+    and pooling is refused (QST_ERR_STATE); one more step stores one."""
+    p = synth.make_problem("c2")
+    for kw in (dict(n_steps=30, burn_in=30), dict(n_steps=30, thin=31), dict(n_steps=30, thin=7, burn_in=28)):
+        P = qst.Problem(2, p.counts)
+        P.run(qst.RunConfig(n_chains=16, seed=3, beta0=0.05, **kw))
+        assert np.all(P.state()[3] == 0), kw
+        with pytest.raises(qst.QstError) as e:
+            P.pool()
+        assert e.value.status == qst.QST_ERR_STATE and "no stored samples" in str(e.value)
+    P = qst.Problem(2, p.counts)
+    P.run(qst.RunConfig(n_chains=16, n_steps=31, seed=3, beta0=0.05, burn_in=30))
+    assert np.all(P.state()[3] == 1) and P.pool()["n_samples"] == 16
+
+
 def test_resume_is_bitwise():
     p = synth.make_problem("c2")
     kw = dict(n_chains=64, seed=9, beta0=0.05, adapt_every=50, thin=2, burn_in=20)
