@@ -4,7 +4,7 @@
 One bench step = the whole hot path on the 4-qubit workload: initialise
 65536 chains (step 0), run 10^4 pCN steps of Algorithm 2 on each (proposal,
 rho, Pauli probabilities, FP64 log-likelihood, accept, adaptation, moments,
-recording of 256 chains every 8 steps) in one persistent launch, then pool
+recording of 256 chains every 4 steps) in one persistent launch, then pool
 (Eq. (BME2)).  Inputs are synthetic (seeded multinomial counts of
 0.95|GHZ_4><GHZ_4| + 0.05 I/16, 1024 shots x 81 settings) and resident in HBM.
 
@@ -117,9 +117,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash, key):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
-    was taken on the current kernel sources; else None."""
+def measured_counter(kernel_hash, key, field):
+    """A figure from the committed rocprofv3 --pmc summaries
+    (profiles/traffic.json), if they were taken on the current kernel
+    sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -128,7 +129,27 @@ def measured_traffic(kernel_hash, key):
     ent = data.get(key)
     if not ent or ent.get("kernel_source_hash") != kernel_hash:
         return None
-    return ent.get("bytes_per_launch")
+    return ent.get(field)
+
+
+def measured_traffic(kernel_hash, key):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return measured_counter(kernel_hash, key, "bytes_per_launch")
+
+
+def valu_issue(kernel_hash, key, chain_steps_per_s):
+    """Vector-instruction issue of the chain launch: the profiled
+    SQ_INSTS_VALU per chain-step (one count per wavefront instruction) times
+    the live chain-step rate, against the issue peak of wave64 VALU work,
+    one wavefront instruction per 4 cycles on each 16-lane SIMD (256 CUs x 4
+    SIMDs x 2.4 GHz / 4); None without a profile of the current sources."""
+    per_step = measured_counter(kernel_hash, key + "_valu", "valu_instr_per_chain_step")
+    if per_step is None:
+        return None
+    peak = 256 * 4 * 2.4e9 / 4
+    achieved = per_step * chain_steps_per_s
+    return {"instr_per_chain_step": per_step, "achieved_per_s": achieved, "peak_per_s": peak,
+            "frac": achieved / peak, "source": measured_counter(kernel_hash, key + "_valu", "summary")}
 
 
 def dense_gemm_rates(qst, synth, torch, prob, n_states=65536, reps=5):
@@ -707,6 +728,8 @@ def main():
                      "flop_per_chain_step": flop, "chain_steps_per_launch": chain_steps,
                      "all_arith_flop_per_chain_step": flop_all,
                      "all_arith_frac": flop_all * chain_steps / (ms_kernel / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
+                     "valu_issue": valu_issue(khash, f"chain_kernel_q{Q}_{args.config}",
+                                              chain_steps / (ms_kernel / 1e3)),
                      "kernel_source_hash": khash},
     }
     if not args.no_forms:
